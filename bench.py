@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Throughput of the fused Navier-Stokes RK3 step on one MI355X.
+
+Workload: the Taylor-Green vortex of the OpenSBLI paper (Sec. "3D Taylor-Green
+vortex") at 512^3, FP64, 4th-order central differences, low-storage RK3 with the
+paper's time step for that grid (3.385e-3 at 64^3, halved per doubling).  A step
+is one pass of the whole hot path: three fused residual + RK-update stages over
+the full grid.  The state starts resident in HBM.
+
+Prints ONE JSON line on stdout.  Extra measurements (FP32 state, order 8) and the
+CPU oracle baseline are attached to the same line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E peak, GB/s
+WORDS_PER_POINT_STEP = 50      # algorithmic words per point per RK3 step (15 + 20 + 15)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def measure(sbli, torch, n, order, dtype, steps, warmup):
+    """Time `steps` RK3 steps after `warmup`; returns a dict of results."""
+    import synth
+    s = sbli.Solver(n, order=order, dtype=dtype, **synth.TGV)
+    q, qt, dq = s.empty_state(), s.empty_state(), s.empty_state()
+    s.tgv_init(q)
+    dt = synth.tgv_dt(n)
+    stream = torch.cuda.current_stream()
+    if warmup:
+        s.rk3_step(q, qt, dq, dt, warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    s.rk3_step(q, qt, dq, dt, steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    diag, code = s.diagnostics(q, check=False)
+    P = n ** 3
+    word = 8 if dtype == "f64" else 4
+    launches = 3 * steps
+    avg_launch_ms = ms / launches
+    bytes_per_launch = WORDS_PER_POINT_STEP * word * P / 3.0
+    achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9
+    del q, qt, dq
+    s.close()
+    torch.cuda.empty_cache()
+    return dict(n=n, order=order, dtype=dtype, steps=steps, ms=ms, ms_per_step=ms / steps,
+                value=P * steps / (ms * 1e-3) / 1e6, avg_launch_ms=avg_launch_ms,
+                bytes_per_launch=bytes_per_launch, achieved_gbs=achieved,
+                frac=achieved / HBM_PEAK_GBS, diag_status=code, Ek=diag["Ek"],
+                enstrophy=diag["enstrophy"])
+
+
+def cpu_baseline(n=256, order=4):
+    """The FP64 oracle, as it stands, on the host cores: one RK3 step of TGV n^3."""
+    import oracle
+    import synth
+    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
+    q = oracle.tgv_init(p)
+    t0 = time.perf_counter()
+    oracle.rk3(q, p, synth.tgv_dt(n), 1)
+    t = time.perf_counter() - t0
+    return {"value": n ** 3 / t / 1e6, "unit": "Mpoint-RK3-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "1 RK3 step of the Taylor-Green state at %d^3, order %d, FP64 (whole-array C "
+                      "oracle, OpenMP over z-planes); %.1f s" % (n, order, t)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--order", type=int, default=4)
+    ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and order-8 lines")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=256)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    from paper_1609_01277_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    import paper_1609_01277_amd as sbli
+
+    log("main: TGV %d^3 %s order %d, %d steps after %d warm-up" % (args.n, args.dtype, args.order,
+                                                                  args.steps, args.warmup))
+    main_r = measure(sbli, torch, args.n, args.order, args.dtype, args.steps, args.warmup)
+    log("main: %.1f Mpt-steps/s, %.3f ms/step, %.0f GB/s (%.1f%% of HBM peak)" % (
+        main_r["value"], main_r["ms_per_step"], main_r["achieved_gbs"], 100 * main_r["frac"]))
+
+    extra = {}
+    if not args.no_extra:
+        for (dt_, order) in (("f32", args.order), ("f64", 8)):
+            if dt_ == args.dtype and order == args.order:
+                continue
+            r = measure(sbli, torch, args.n, order, dt_, args.steps, args.warmup)
+            key = "%s_order%d" % (dt_, order)
+            extra[key] = {k: r[k] for k in ("value", "ms_per_step", "achieved_gbs", "frac")}
+            log("extra %s: %.1f Mpt-steps/s, %.0f GB/s (%.1f%%)" % (key, r["value"], r["achieved_gbs"],
+                                                                    100 * r["frac"]))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle, 1 step at %d^3" % args.cpu_n)
+        cpu = cpu_baseline(args.cpu_n, args.order)
+        log("cpu baseline: %.2f Mpt-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    word = 8 if args.dtype == "f64" else 4
+    line = {
+        "metric": "Mpoint-RK3-steps/s, 4th-order TGV 512^3 FP64 vs FP32; % of HBM roofline",
+        "value": main_r["value"],
+        "unit": "Mpoint-RK3-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (analytic Taylor-Green initial state)",
+        "config": {"workload": "Taylor-Green vortex %d^3, order %d, %s state, low-storage RK3, dt %.6g"
+                               % (args.n, args.order, args.dtype.upper(), 64 * 3.385e-3 / args.n),
+                   "n": args.n, "order": args.order, "points": args.n ** 3},
+        "roofline": {"bound": "hbm", "achieved": main_r["achieved_gbs"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": main_r["frac"], "traffic": None,
+                     "kernel": "RK3 stage (residual + update), all launches of the timed region",
+                     "algorithmic_bytes_per_launch": main_r["bytes_per_launch"],
+                     "avg_launch_ms": main_r["avg_launch_ms"],
+                     "words_per_point_step": WORDS_PER_POINT_STEP, "word_bytes": word},
+        "cpu_baseline": cpu,
+        "extra": extra,
+        "diagnostics_after_run": {"Ek": main_r["Ek"], "enstrophy": main_r["enstrophy"],
+                                  "status": main_r["diag_status"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

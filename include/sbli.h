@@ -1,0 +1,131 @@
+/*
+ * sbli.h -- C ABI of libsbli.so, an MI355X (gfx950) implementation of the
+ * explicit residual evaluation and low-storage RK3 time stepping of the 3D
+ * compressible Navier-Stokes equations described in Jacobs, Jammy & Sandham,
+ * "OpenSBLI" (arXiv:1609.01277).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Status: every call returns an int, SBLI_OK (0) on success and a negative
+ *    SBLI_ERR_* code otherwise.  No call aborts the process; after an error,
+ *    sbli_last_error() returns a human-readable message for that context.
+ *  - Memory: the caller allocates and owns every state-sized buffer; all state
+ *    pointers are DEVICE pointers.  The library owns only the context and small
+ *    device scratch (reduction partials), allocated in sbli_init.
+ *  - Layout of a state q: five fields back to back, q[f][z][y][x], x fastest,
+ *    f = (rho, rho*u, rho*v, rho*w, rho*E); element type double (SBLI_F64) or
+ *    float (SBLI_F32) as chosen at init; nx*ny*nz*5 elements.
+ *  - Streams: all device work is enqueued on the hipStream_t given at init
+ *    (pass NULL for the default stream).  Calls return without waiting unless
+ *    stated otherwise.
+ *  - Grid: x_i = i*lx/nx (same in y, z) on a periodic box; the domain is
+ *    [0, lx) x [0, ly) x [0, lz) and the reference length L = 1.
+ */
+#ifndef SBLI_H
+#define SBLI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SBLI_OK 0
+#define SBLI_ERR_ARG (-1)         /* invalid argument (message says which)            */
+#define SBLI_ERR_HIP (-2)         /* a HIP runtime call failed                        */
+#define SBLI_ERR_NONFINITE (-3)   /* diagnostics found NaN/Inf, rho <= 0 or p <= 0    */
+#define SBLI_ERR_ALLOC (-4)       /* device or host allocation failed                 */
+#define SBLI_ERR_UNSUPPORTED (-5) /* a valid request this build does not implement    */
+
+#define SBLI_F64 0
+#define SBLI_F32 1
+
+/*
+ * Problem statement (paper Sec. "Grid" and Sec. "3D Taylor-Green vortex"):
+ * grid points per axis, box lengths, Reynolds, Mach and Prandtl numbers, ratio
+ * of specific heats, central-difference order and the state element type.
+ * Requirements: order in {2, 4, 6, 8}; every n >= 2*order + 1 (the nested
+ * derivative terms reach 2*(order/2) points each way); lengths, Re, Mach, Pr > 0;
+ * gamma > 1; dtype SBLI_F64 or SBLI_F32.
+ */
+typedef struct sbli_params {
+    int nx, ny, nz;
+    double lx, ly, lz;
+    double Re, Mach, Pr, gamma;
+    int order;
+    int dtype;
+} sbli_params;
+
+typedef struct sbli_ctx sbli_ctx;
+
+/*
+ * sbli_init: validate `p`, derive the grid spacing, build the central
+ * difference weights of the requested order (Sec. "Discretisation schemes":
+ * arbitrary-order central first and second derivatives, rationals evaluated
+ * once) and the reciprocal constants (1/Re, heat-flux coefficient
+ * 1/((gamma-1) M^2 Pr Re) with mu = 1).  `hip_stream` is a hipStream_t (or
+ * NULL).  On success *out receives a new context, to be released with
+ * sbli_destroy.  On failure *out is set to NULL and the message is available
+ * from sbli_last_error(NULL).
+ */
+int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out);
+
+/* Release a context and its scratch; waits for its stream first.  NULL is a no-op. */
+int sbli_destroy(sbli_ctx* ctx);
+
+/* Message of the last failed call on `ctx` (or of the last failed sbli_init when
+ * ctx is NULL).  The string is owned by the library. */
+const char* sbli_last_error(const sbli_ctx* ctx);
+
+/*
+ * sbli_tgv_init: write the Taylor-Green initial state (Sec. "3D Taylor-Green
+ * vortex", initial conditions, with rho = 1) into the device state `q`:
+ *   u = sin X cos Y cos Z, v = -cos X sin Y cos Z, w = 0,
+ *   p = 1/(gamma M^2) + (cos 2X + cos 2Y)(cos 2Z + 2)/16,
+ *   rho E = p/(gamma-1) + rho |u|^2 / 2,
+ * at X = x_i + phase[0], Y = y_j + phase[1], Z = z_k + phase[2].  `phase` is a
+ * host array of three doubles or NULL (no shift).
+ */
+int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase);
+
+/*
+ * sbli_rhs: rhs = dq/dt of the compressible Navier-Stokes equations (eq. mass,
+ * momentum, energy; stress tensor; heat flux; eq. eos; total energy) with the
+ * skew-symmetric convective form (eq. skew_symmetric_formulation), the viscous
+ * Laplacian by the second-derivative stencil, nested derivatives inner-first,
+ * periodic in every direction.  `q` and `rhs` are device states of the context's
+ * dtype and must not overlap.
+ */
+int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs);
+
+/*
+ * sbli_rk3_step: advance `q` by `nsteps` steps of the three-stage low-storage
+ * third-order Runge-Kutta scheme (Sec. "Discretisation schemes"), in 2N form
+ *   dq <- A_k dq + dt R(q),  q <- q + B_k dq,  A = (0, -5/9, -153/128),
+ *   B = (1/3, 15/16, 8/15).
+ * `q_tmp` and `dq` are caller-provided device workspaces of the state's size;
+ * `q`, `q_tmp` and `dq` must be three distinct, non-overlapping buffers.  The
+ * result is in `q` on return (stream-ordered).  The contents of q_tmp and dq
+ * afterwards are unspecified.  nsteps >= 0; dt finite.
+ */
+int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int nsteps);
+
+/*
+ * sbli_diagnostics: volume averages of the state (Sec. "3D Taylor-Green
+ * vortex", kinetic energy and enstrophy integrals, rho_ref = 1), computed in
+ * FP64 with compensated summation whatever the state dtype:
+ *   out[0] = E_k = <1/2 rho u_j u_j>
+ *   out[1] = enstrophy = <1/2 rho |omega|^2>, omega = curl u with the context's
+ *            order-p central first derivative
+ *   out[2..6] = <rho>, <rho u>, <rho v>, <rho w>, <rho E>
+ * where <f> = sum over the grid / (nx ny nz).  `out` is a host array of 7
+ * doubles.  Synchronises the stream.  Returns SBLI_ERR_NONFINITE (with `out`
+ * filled) if any value is NaN/Inf or any point has rho <= 0 or p <= 0.
+ */
+int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SBLI_H */

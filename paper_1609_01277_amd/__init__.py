@@ -1,0 +1,94 @@
+"""MI355X (gfx950) compressible Navier-Stokes hot path after OpenSBLI (arXiv:1609.01277).
+
+The solver lives in libsbli.so (hand-written HIP kernels behind a C ABI,
+include/sbli.h).  This package is the thin Python side: ctypes marshalling
+(`_lib`, functions named like the C entry points) and a `Solver` convenience
+class that uses PyTorch only to allocate device memory and to pick the stream.
+"""
+import math
+
+from . import _lib
+from ._lib import (SBLI_ERR_ALLOC, SBLI_ERR_ARG, SBLI_ERR_HIP, SBLI_ERR_NONFINITE,  # noqa: F401
+                   SBLI_ERR_UNSUPPORTED, SBLI_F32, SBLI_F64, SBLI_OK, SbliError, sbli_destroy,
+                   sbli_diagnostics, sbli_init, sbli_last_error, sbli_params, sbli_rhs,
+                   sbli_rk3_step, sbli_tgv_init)
+
+__all__ = ["Solver", "make_params", "SbliError", "sbli_init", "sbli_destroy", "sbli_last_error",
+           "sbli_tgv_init", "sbli_rhs", "sbli_rk3_step", "sbli_diagnostics", "sbli_params"]
+
+DIAG_NAMES = ("Ek", "enstrophy", "rho", "rhou", "rhov", "rhow", "rhoE")
+
+
+def make_params(n, order=4, dtype="f64", Re=1600.0, Mach=0.1, Pr=0.71, gamma=1.4, length=None):
+    """sbli_params for an n = (nx, ny, nz) (or int) periodic box of side 2*pi (default)."""
+    if isinstance(n, int):
+        n = (n, n, n)
+    if length is None:
+        length = (2 * math.pi,) * 3
+    dt = {"f64": SBLI_F64, "f32": SBLI_F32}[dtype]
+    return sbli_params(int(n[0]), int(n[1]), int(n[2]), float(length[0]), float(length[1]),
+                       float(length[2]), float(Re), float(Mach), float(Pr), float(gamma), int(order),
+                       dt)
+
+
+class Solver:
+    """One periodic box on the current HIP device and stream.
+
+    State tensors are torch tensors of shape (5, nz, ny, nx), dtype float64 or
+    float32, on the GPU, contiguous.
+    """
+
+    def __init__(self, n, order=4, dtype="f64", Re=1600.0, Mach=0.1, Pr=0.71, gamma=1.4,
+                 length=None, stream=None):
+        import torch
+        self.torch = torch
+        self.params = make_params(n, order, dtype, Re, Mach, Pr, gamma, length)
+        self.shape = (5, self.params.nz, self.params.ny, self.params.nx)
+        self.dtype = torch.float64 if dtype == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.ctx = sbli_init(self.params, stream.cuda_stream)
+
+    def close(self):
+        if self.ctx:
+            sbli_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_state(self):
+        return self.torch.empty(self.shape, dtype=self.dtype, device="cuda")
+
+    def _check_state(self, t, name):
+        if not (t.is_cuda and t.is_contiguous() and tuple(t.shape) == self.shape and t.dtype == self.dtype):
+            raise ValueError("%s must be a contiguous CUDA tensor of shape %r and dtype %s"
+                             % (name, self.shape, self.dtype))
+
+    def tgv_init(self, q, phase=None):
+        self._check_state(q, "q")
+        sbli_tgv_init(self.ctx, q, phase)
+        return q
+
+    def rhs(self, q, out=None):
+        self._check_state(q, "q")
+        if out is None:
+            out = self.empty_state()
+        self._check_state(out, "out")
+        sbli_rhs(self.ctx, q, out)
+        return out
+
+    def rk3_step(self, q, q_tmp, dq, dt, nsteps=1):
+        for t, nm in ((q, "q"), (q_tmp, "q_tmp"), (dq, "dq")):
+            self._check_state(t, nm)
+        sbli_rk3_step(self.ctx, q, q_tmp, dq, dt, nsteps)
+        return q
+
+    def diagnostics(self, q, check=True):
+        self._check_state(q, "q")
+        vals, code = sbli_diagnostics(self.ctx, q, check=check)
+        return dict(zip(DIAG_NAMES, vals)), code

@@ -1,0 +1,273 @@
+// libsbli: host side of the C ABI declared in include/sbli.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/sbli.h"
+#include "kernels_pointwise.h"
+#include "kernels_stage_simple.h"
+#include "stencil_weights.h"
+
+using namespace sbli;
+
+struct sbli_ctx {
+    sbli_params p;
+    hipStream_t stream;
+    int device;
+    int r;
+    double h[3];
+    double a[kMaxR], c0, c[kMaxR];
+    BoxConst<double> c64;
+    BoxConst<float> c32;
+    void* W;                // nested-derivative fields, 6 * P elements of the state type
+    double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
+    double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
+    double* diag_out;       // 10 doubles
+    std::string err;
+};
+
+static std::string g_init_err;
+
+static int fail(sbli_ctx* ctx, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    else g_init_err = buf;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                          \
+    do {                                                                                            \
+        hipError_t e_ = (call);                                                                     \
+        if (e_ != hipSuccess) return fail(ctx, SBLI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+template <typename T>
+static void fill_const(const sbli_ctx* x, BoxConst<T>& c) {
+    c.n[0] = x->p.nx;
+    c.n[1] = x->p.ny;
+    c.n[2] = x->p.nz;
+    c.P = (int64_t)x->p.nx * x->p.ny * x->p.nz;
+    for (int d = 0; d < 3; ++d) {
+        for (int m = 0; m < kMaxR; ++m) {
+            c.da[d][m] = (T)(m < x->r ? x->a[m] / x->h[d] : 0.0);
+            c.d2c[d][m] = (T)(m < x->r ? x->c[m] / (x->h[d] * x->h[d]) : 0.0);
+        }
+        c.d2c0[d] = (T)(x->c0 / (x->h[d] * x->h[d]));
+    }
+    const double g = x->p.gamma, M = x->p.Mach;
+    c.gm1 = (T)(g - 1.0);
+    c.gM2 = (T)(g * M * M);
+    c.inv_Re = (T)(1.0 / x->p.Re);
+    c.inv_3Re = (T)(1.0 / (3.0 * x->p.Re));
+    c.inv_Re23 = (T)(2.0 / (3.0 * x->p.Re));
+    c.kappa = (T)(1.0 / ((g - 1.0) * M * M * x->p.Pr * x->p.Re));
+}
+
+static size_t elem_size(const sbli_ctx* x) { return x->p.dtype == SBLI_F32 ? sizeof(float) : sizeof(double); }
+static int64_t npoints(const sbli_ctx* x) { return (int64_t)x->p.nx * x->p.ny * x->p.nz; }
+
+static bool overlaps(const void* a, const void* b, size_t bytes) {
+    const char* pa = (const char*)a;
+    const char* pb = (const char*)b;
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out) {
+    if (!out) return fail(nullptr, SBLI_ERR_ARG, "sbli_init: out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, SBLI_ERR_ARG, "sbli_init: params is NULL");
+    if (p->order != 2 && p->order != 4 && p->order != 6 && p->order != 8)
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: order must be 2, 4, 6 or 8 (got %d)", p->order);
+    const int nmin = 2 * p->order + 1;
+    if (p->nx < nmin || p->ny < nmin || p->nz < nmin)
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: every grid size must be >= %d for order %d (got %d x %d x %d)",
+                    nmin, p->order, p->nx, p->ny, p->nz);
+    if ((double)p->nx * p->ny * p->nz * 5.0 > 9.0e18)
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: grid too large");
+    if (!(p->lx > 0 && p->ly > 0 && p->lz > 0 && std::isfinite(p->lx) && std::isfinite(p->ly) && std::isfinite(p->lz)))
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: box lengths must be finite and > 0");
+    if (!(p->Re > 0 && p->Mach > 0 && p->Pr > 0 && std::isfinite(p->Re) && std::isfinite(p->Mach) && std::isfinite(p->Pr)))
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: Re, Mach and Pr must be finite and > 0");
+    if (!(p->gamma > 1.0 && std::isfinite(p->gamma)))
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: gamma must be finite and > 1");
+    if (p->dtype != SBLI_F64 && p->dtype != SBLI_F32)
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: dtype must be SBLI_F64 or SBLI_F32");
+
+    sbli_ctx* x = new (std::nothrow) sbli_ctx();
+    if (!x) return fail(nullptr, SBLI_ERR_ALLOC, "sbli_init: out of host memory");
+    x->p = *p;
+    x->stream = (hipStream_t)hip_stream;
+    x->r = p->order / 2;
+    x->h[0] = p->lx / p->nx;
+    x->h[1] = p->ly / p->ny;
+    x->h[2] = p->lz / p->nz;
+    central_weights(x->r, x->a, &x->c0, x->c);
+    fill_const(x, x->c64);
+    fill_const(x, x->c32);
+
+    hipError_t e = hipGetDevice(&x->device);
+    const size_t wbytes = 6 * (size_t)npoints(x) * elem_size(x);
+    if (e == hipSuccess) e = hipMalloc(&x->W, wbytes);
+    if (e == hipSuccess) e = hipMalloc((void**)&x->diag_part, sizeof(double) * kDiagBlocks * (2 * kDiagQ + 3));
+    if (e == hipSuccess) e = hipMalloc((void**)&x->diag_da, sizeof(double) * 3 * kMaxR);
+    if (e == hipSuccess) e = hipMalloc((void**)&x->diag_out, sizeof(double) * 10);
+    if (e == hipSuccess) {
+        double da[3 * kMaxR];
+        for (int d = 0; d < 3; ++d)
+            for (int m = 0; m < kMaxR; ++m) da[d * kMaxR + m] = m < x->r ? x->a[m] / x->h[d] : 0.0;
+        e = hipMemcpyAsync(x->diag_da, da, sizeof(da), hipMemcpyHostToDevice, x->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(x->stream);
+    }
+    if (e != hipSuccess) {
+        int code = (e == hipErrorOutOfMemory) ? SBLI_ERR_ALLOC : SBLI_ERR_HIP;
+        fail(nullptr, code, "sbli_init: %s", hipGetErrorString(e));
+        hipFree(x->W);
+        hipFree(x->diag_part);
+        hipFree(x->diag_da);
+        hipFree(x->diag_out);
+        delete x;
+        return code;
+    }
+    *out = x;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_destroy(sbli_ctx* ctx) {
+    if (!ctx) return SBLI_OK;
+    hipStreamSynchronize(ctx->stream);
+    hipFree(ctx->W);
+    hipFree(ctx->diag_part);
+    hipFree(ctx->diag_da);
+    hipFree(ctx->diag_out);
+    delete ctx;
+    return SBLI_OK;
+}
+
+extern "C" const char* sbli_last_error(const sbli_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_init_err.c_str();
+}
+
+extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_tgv_init: ctx is NULL");
+    if (!q) return fail(ctx, SBLI_ERR_ARG, "sbli_tgv_init: q is NULL");
+    const double ph[3] = {phase ? phase[0] : 0.0, phase ? phase[1] : 0.0, phase ? phase[2] : 0.0};
+    const int64_t P = npoints(ctx);
+    const unsigned blocks = (unsigned)((P + 255) / 256);
+    if (ctx->p.dtype == SBLI_F64)
+        tgv_init_kernel<double><<<blocks, 256, 0, ctx->stream>>>((double*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->h[0],
+                                                                 ctx->h[1], ctx->h[2], ph[0], ph[1], ph[2],
+                                                                 ctx->p.gamma, ctx->p.Mach);
+    else
+        tgv_init_kernel<float><<<blocks, 256, 0, ctx->stream>>>((float*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, ctx->h[0],
+                                                                ctx->h[1], ctx->h[2], ph[0], ph[1], ph[2],
+                                                                ctx->p.gamma, ctx->p.Mach);
+    HIP_TRY(ctx, hipGetLastError());
+    return SBLI_OK;
+}
+
+template <typename T, int R>
+static void launch_stage(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, int mode, T dt, T A, T B) {
+    const unsigned blocks = (unsigned)((c.P + 255) / 256);
+    T* W = (T*)ctx->W;
+    grad_kernel<T, R><<<blocks, 256, 0, ctx->stream>>>(qin, W, c);
+    switch (mode) {
+        case kModeRHS: stage_kernel<T, R, kModeRHS><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
+        case kModeStage1: stage_kernel<T, R, kModeStage1><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
+        case kModeStage2: stage_kernel<T, R, kModeStage2><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
+        default: stage_kernel<T, R, kModeStage3><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
+    }
+}
+
+template <typename T>
+static void launch_stage_r(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, int mode, T dt, T A, T B) {
+    switch (ctx->r) {
+        case 1: launch_stage<T, 1>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
+        case 2: launch_stage<T, 2>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
+        case 3: launch_stage<T, 3>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
+        default: launch_stage<T, 4>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
+    }
+}
+
+static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
+    if (ctx->p.dtype == SBLI_F64)
+        launch_stage_r<double>(ctx, ctx->c64, (const double*)qin, (double*)dq, (double*)qout, mode, dt, A, B);
+    else
+        launch_stage_r<float>(ctx, ctx->c32, (const float*)qin, (float*)dq, (float*)qout, mode, (float)dt, (float)A,
+                              (float)B);
+}
+
+extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_rhs: ctx is NULL");
+    if (!q || !rhs) return fail(ctx, SBLI_ERR_ARG, "sbli_rhs: NULL state pointer");
+    const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
+    if (overlaps(q, rhs, bytes)) return fail(ctx, SBLI_ERR_ARG, "sbli_rhs: q and rhs overlap");
+    launch_any(ctx, q, nullptr, rhs, kModeRHS, 0.0, 0.0, 0.0);
+    HIP_TRY(ctx, hipGetLastError());
+    return SBLI_OK;
+}
+
+// Williamson's 2N-storage coefficients of the three-stage third-order scheme.
+static const double kRK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+static const double kRK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+
+extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int nsteps) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_rk3_step: ctx is NULL");
+    if (!q || !q_tmp || !dq) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: NULL state pointer");
+    if (nsteps < 0) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: nsteps < 0");
+    if (!std::isfinite(dt)) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: dt is not finite");
+    const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
+    if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
+        return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: q, q_tmp and dq must not overlap");
+    void* src = q;
+    void* dst = q_tmp;
+    for (int s = 0; s < nsteps; ++s) {
+        for (int k = 0; k < 3; ++k) {
+            launch_any(ctx, src, dq, dst, kModeStage1 + k, dt, kRK_A[k], kRK_B[k]);
+            void* t = src;
+            src = dst;
+            dst = t;
+        }
+    }
+    HIP_TRY(ctx, hipGetLastError());
+    if (src != q) HIP_TRY(ctx, hipMemcpyAsync(q, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_diagnostics: ctx is NULL");
+    if (!q || !out) return fail(ctx, SBLI_ERR_ARG, "sbli_diagnostics: NULL pointer");
+    const int nb = kDiagBlocks;
+    const double gm1 = ctx->p.gamma - 1.0;
+    const int r = ctx->r;
+#define DIAG_LAUNCH(T, RR)                                                                                      \
+    diag_partial_kernel<T, RR><<<nb, kDiagThreads, 0, ctx->stream>>>((const T*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, \
+                                                                     ctx->diag_da, gm1, ctx->diag_part)
+    if (ctx->p.dtype == SBLI_F64) {
+        if (r == 1) DIAG_LAUNCH(double, 1); else if (r == 2) DIAG_LAUNCH(double, 2);
+        else if (r == 3) DIAG_LAUNCH(double, 3); else DIAG_LAUNCH(double, 4);
+    } else {
+        if (r == 1) DIAG_LAUNCH(float, 1); else if (r == 2) DIAG_LAUNCH(float, 2);
+        else if (r == 3) DIAG_LAUNCH(float, 3); else DIAG_LAUNCH(float, 4);
+    }
+#undef DIAG_LAUNCH
+    HIP_TRY(ctx, hipGetLastError());
+    diag_final_kernel<<<1, kDiagThreads, 0, ctx->stream>>>(ctx->diag_part, nb, 1.0 / (double)npoints(ctx), ctx->diag_out);
+    HIP_TRY(ctx, hipGetLastError());
+    double res[10];
+    HIP_TRY(ctx, hipMemcpyAsync(res, ctx->diag_out, sizeof(res), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    for (int d = 0; d < 7; ++d) out[d] = res[d];
+    if (res[7] > 0 || res[8] > 0 || res[9] > 0)
+        return fail(ctx, SBLI_ERR_NONFINITE, "sbli_diagnostics: %.0f non-finite values, %.0f points with rho <= 0, %.0f with p <= 0",
+                    res[7], res[8], res[9]);
+    return SBLI_OK;
+}

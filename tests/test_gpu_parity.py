@@ -1,0 +1,180 @@
+"""GPU parity of libsbli (through the C ABI) against the FP64 oracle.
+
+Bar (FP64): per field, ||q_gpu - q_oracle||_inf / ||q_oracle||_inf <= 1e-12 after every
+step, the three momentum components normalised by their common maximum (rho w starts
+at exactly zero).  Inputs are built on the oracle side (or drawn from `synth`) and
+uploaded, so both sides start from the same numbers.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _sbli():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a HIP device")
+    import paper_1609_01277_amd as sbli
+    return sbli, torch
+
+
+def rel_err(got, ref):
+    """Per-field relative max error, momentum normalised by the largest momentum."""
+    mom = np.abs(ref[1:4]).max()
+    out = []
+    for f in range(5):
+        scale = mom if f in (1, 2, 3) else np.abs(ref[f]).max()
+        out.append(np.abs(got[f] - ref[f]).max() / max(scale, 1e-300))
+    return out
+
+
+def to_dev(torch, q, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(q))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+@pytest.mark.parametrize("n", [(32, 32, 32), (20, 24, 36), (17, 19, 18)])
+def test_tgv_init_matches_oracle(oracle_mod, n):
+    sbli, torch = _sbli()
+    p = oracle.Params(n=n, order=4, **synth.TGV)
+    ref = oracle.tgv_init(p, phase=(0.3, 1.1, 2.0))
+    s = sbli.Solver(n, order=4, **synth.TGV)
+    q = s.tgv_init(s.empty_state(), phase=(0.3, 1.1, 2.0))
+    got = q.cpu().numpy()
+    assert np.abs(got - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("order", [2, 4, 6, 8])
+@pytest.mark.parametrize("n", [(32, 32, 32), (20, 24, 36), (17, 18, 19)])
+def test_rhs_matches_oracle_random_state(oracle_mod, order, n):
+    sbli, torch = _sbli()
+    if min(n) < 2 * order + 1:
+        pytest.skip("grid smaller than the stencil footprint")
+    q0 = synth.random_conservative_state(n, seed=100 + order)
+    p = oracle.Params(n=n, order=order, **synth.TGV)
+    ref = oracle.rhs(q0, p)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    R = s.rhs(to_dev(torch, q0))
+    errs = rel_err(R.cpu().numpy(), ref)
+    assert max(errs) <= TOL64, errs
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_rk3_tgv32_every_step(oracle_mod, order):
+    """32^3 Taylor-Green, FP64, 10 steps of dt = 3.385e-3: parity after every step."""
+    sbli, torch = _sbli()
+    n, dt = 32, 3.385e-3
+    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
+    qo = oracle.tgv_init(p)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    q = to_dev(torch, qo)
+    qt, dq = s.empty_state(), s.empty_state()
+    worst = 0.0
+    for step in range(10):
+        qo = oracle.rk3(qo, p, dt, 1)
+        s.rk3_step(q, qt, dq, dt, 1)
+        errs = rel_err(q.cpu().numpy(), qo)
+        worst = max(worst, max(errs))
+        assert max(errs) <= TOL64, (step, errs)
+    print("max relative error over 10 steps: %.3e" % worst)
+
+
+def test_rk3_multi_step_call_equals_single_steps(oracle_mod):
+    """One call with nsteps = 4 (even: no final copy) and nsteps = 3 (odd) vs the oracle."""
+    sbli, torch = _sbli()
+    n, dt, order = (24, 20, 28), 2e-3, 4
+    q0 = synth.random_conservative_state(n, seed=7, mom=0.5)
+    p = oracle.Params(n=n, order=order, **synth.TGV)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    for k in (3, 4):
+        ref = oracle.rk3(q0, p, dt, k)
+        q = to_dev(torch, q0)
+        s.rk3_step(q, s.empty_state(), s.empty_state(), dt, k)
+        errs = rel_err(q.cpu().numpy(), ref)
+        assert max(errs) <= TOL64, (k, errs)
+
+
+def _diag_close(got, ref, scale):
+    return abs(got - ref) <= 1e-12 * max(abs(ref), scale)
+
+
+@pytest.mark.parametrize("order", [4, 8])
+def test_diagnostics_match_oracle(oracle_mod, order):
+    sbli, torch = _sbli()
+    n = (32, 32, 32)
+    p = oracle.Params(n=n, order=order, **synth.TGV)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    q0 = oracle.tgv_init(p)
+    for q in (q0, q0 + 0.01 * synth.smooth_random_perturbation(32, seed=4)):
+        ref, flags = oracle.diagnostics(q, p)
+        assert flags == (0, 0, 0)
+        got, code = s.diagnostics(to_dev(torch, q))
+        assert code == sbli.SBLI_OK
+        vals = list(got.values())
+        for k in range(7):
+            scale = 1.0 if k != 6 else 180.0
+            assert _diag_close(vals[k], ref[k], scale), (k, vals[k], ref[k])
+
+
+def test_diagnostics_flag_nonfinite_and_negative(oracle_mod):
+    sbli, torch = _sbli()
+    n = 24
+    p = oracle.Params(n=(n, n, n), order=4, **synth.TGV)
+    s = sbli.Solver(n, order=4, **synth.TGV)
+    q0 = oracle.tgv_init(p)
+    _, code = s.diagnostics(to_dev(torch, q0))
+    assert code == sbli.SBLI_OK
+    for f, val in ((2, np.nan), (0, -1.0), (4, 0.0), (1, np.inf)):
+        q = q0.copy()
+        q[f, 5, 6, 7] = val
+        _, code = s.diagnostics(to_dev(torch, q), check=False)
+        assert code == sbli.SBLI_ERR_NONFINITE, (f, val)
+        with pytest.raises(sbli.SbliError):
+            s.diagnostics(to_dev(torch, q))
+
+
+FULL = [(256, 4), (256, 8), (512, 4), (512, 8)]
+
+
+@pytest.mark.parametrize("n,order", FULL)
+def test_full_size_sampled_step_parity(oracle_mod, n, order):
+    """Full-size Taylor-Green (256^3, 512^3; orders 4, 8), FP64, one RK3 step with the
+    paper's dt, through the same entry point the benchmark times; sampled points are
+    computed one by one by the oracle.  Conservation sums must not drift."""
+    sbli, torch = _sbli()
+    dt = synth.tgv_dt(n)
+    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
+    print("building oracle TGV state %d^3" % n, flush=True)
+    q0 = oracle.tgv_init(p)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    q = to_dev(torch, q0)
+    qt, dq = s.empty_state(), s.empty_state()
+    d0, _ = s.diagnostics(q)
+    s.rk3_step(q, qt, dq, dt, 1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(n + order)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 1, n - 2), (3, n - 4, n // 3)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(4)]
+    ref = oracle.rk3_at_points(q0, p, dt, pts)
+    idx = torch.tensor([[z, y, x] for (x, y, z) in pts], device="cuda")
+    got = q[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().T
+    scale = np.abs(q0).reshape(5, -1).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    err = (np.abs(got - ref) / scale).max()
+    assert err <= TOL64, err
+    d1, _ = s.diagnostics(q)
+    for name in ("rho", "rhou", "rhov", "rhow", "rhoE"):
+        assert abs(d1[name] - d0[name]) < 1e-13 * max(1.0, abs(d0[name])), name
+    del q, qt, dq
+    s.close()
+    torch.cuda.empty_cache()
