@@ -1,0 +1,387 @@
+// Fused residual + RK3-stage kernel: one launch per stage, the state read once
+// and written once per point (plus dq).
+//
+// Data flow (per workgroup): a TX x TY tile of (x, y) columns marches along z.
+// The nested terms of the residual (viscous work D_j(u_i tau_ij) and the
+// grad-div part D_i(D_k u_k), paper Sec. "Expanding": inner derivative first)
+// need the velocity gradient on a ring of R columns around the tile and R
+// planes ahead of the output plane, so every stage is a three-step pipeline per
+// z-plane:
+//   1. each column thread loads the state R planes ahead of the gradient plane
+//      and keeps a register window of 3R+1 planes of point fields
+//      (rho, rho u_i, rho E, u_i, p, T);
+//   2. the "gradient" plane a: velocity gradient by x/y stencils over an LDS
+//      plane of u (tile + 2R ring) and z stencils over the register window,
+//      reduced at once to the six fields the outer derivatives act on
+//      (V_j = u_i tau_ij and theta - D_j u_j), kept in register windows;
+//   3. the output plane o = a - R: every x/y derivative from an LDS plane of
+//      point fields (tile + R ring), every z derivative from the register
+//      windows, the residual, and the RK update written straight to HBM.
+// Columns of the R-ring around the tile are handled by extra "halo" threads
+// (whole wavefronts apart from the interior ones); the 2R-ring of u needed only
+// for the x/y gradient stencils of halo columns is loaded directly.  Periodic
+// wrap is folded into the column coordinates, so ragged tiles need no special
+// case beyond masking their stores.
+#pragma once
+
+#include "sbli_common.h"
+
+namespace sbli {
+
+template <int R, int TX, int TY>
+struct FusedShape {
+    static constexpr int NI = TX * TY;              // interior columns
+    static constexpr int NHX = 2 * R * TY;          // x-ring columns
+    static constexpr int NHY = 2 * R * TX;          // y-ring columns
+    static constexpr int NE1 = NI + NHX + NHY;      // columns with a register window
+    static constexpr int NT = (NE1 + 63) / 64 * 64; // threads per workgroup
+    static constexpr int BX1 = TX + 2 * R, BY1 = TY + 2 * R;  // LDS box of point fields
+    static constexpr int BX2 = TX + 4 * R, BY2 = TY + 4 * R;  // LDS box of u
+    static constexpr int NOUT = 2 * R * TY + 2 * R * TX + 4 * R * R;  // u-only ring points
+    static_assert(NI % 64 == 0, "interior columns must fill whole wavefronts");
+    static_assert(NOUT <= NT, "one u-ring point per thread at most");
+};
+
+// Point fields kept per plane and per column.
+template <typename T>
+struct PF {
+    T rho, m0, m1, m2, E, u0, u1, u2, p, Tm;
+};
+
+template <typename T>
+__device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T gM2) {
+    PF<T> s;
+    s.rho = rho;
+    s.m0 = m0;
+    s.m1 = m1;
+    s.m2 = m2;
+    s.E = E;
+    const T rr = T(1) / rho;
+    s.u0 = m0 * rr;
+    s.u1 = m1 * rr;
+    s.u2 = m2 * rr;
+    s.p = gm1 * (E - T(0.5) * (m0 * s.u0 + m1 * s.u1 + m2 * s.u2));
+    s.Tm = gM2 * s.p * rr;
+    return s;
+}
+
+__device__ __forceinline__ int wrap_mod(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// Number of LDS fields of the output plane: 10 point fields + (V_x, Th_x, V_y, Th_y).
+constexpr int kPlFields = 14;
+
+// Accumulates, for one direction d, the derivative sums of the residual from a
+// neighbour pair (a = +m, b = -m) with weights w (first) and w2 (second).
+template <typename T>
+struct DirSums {
+    T dRho, dM0, dM1, dM2, dF0, dF1, dF2, dE, dH, dU, dTh, d2U0, d2U1, d2U2, d2T;
+    __device__ __forceinline__ void zero() {
+        dRho = dM0 = dM1 = dM2 = dF0 = dF1 = dF2 = dE = dH = dU = dTh = 0;
+        d2U0 = d2U1 = d2U2 = d2T = 0;
+    }
+    // d is the direction (0, 1, 2): selects u_d and which momentum gets 2p.
+    template <int d>
+    __device__ __forceinline__ void add(const PF<T>& a, T Va, T Tha, const PF<T>& b, T Vb, T Thb, T w, T w2) {
+        const T ua = d == 0 ? a.u0 : (d == 1 ? a.u1 : a.u2);
+        const T ub = d == 0 ? b.u0 : (d == 1 ? b.u1 : b.u2);
+        dRho += w * (a.rho - b.rho);
+        dM0 += w * (a.m0 - b.m0);
+        dM1 += w * (a.m1 - b.m1);
+        dM2 += w * (a.m2 - b.m2);
+        T fa0 = a.m0 * ua, fb0 = b.m0 * ub;
+        T fa1 = a.m1 * ua, fb1 = b.m1 * ub;
+        T fa2 = a.m2 * ua, fb2 = b.m2 * ub;
+        if (d == 0) { fa0 += T(2) * a.p; fb0 += T(2) * b.p; }
+        if (d == 1) { fa1 += T(2) * a.p; fb1 += T(2) * b.p; }
+        if (d == 2) { fa2 += T(2) * a.p; fb2 += T(2) * b.p; }
+        dF0 += w * (fa0 - fb0);
+        dF1 += w * (fa1 - fb1);
+        dF2 += w * (fa2 - fb2);
+        dE += w * (a.E - b.E);
+        dH += w * (((a.E + T(2) * a.p) * ua - T(2) * Va) - ((b.E + T(2) * b.p) * ub - T(2) * Vb));
+        dU += w * (ua - ub);
+        dTh += w * (Tha - Thb);
+        d2U0 += w2 * (a.u0 + b.u0);
+        d2U1 += w2 * (a.u1 + b.u1);
+        d2U2 += w2 * (a.u2 + b.u2);
+        d2T += w2 * (a.Tm + b.Tm);
+    }
+    // Adds this direction's part of the residual (paper eq. mass, momentum,
+    // energy in the skew-symmetric form, regrouped by linearity) at point s.
+    template <int d>
+    __device__ __forceinline__ void finish(const PF<T>& s, T c0, const BoxConst<T>& c, T& Rr, T& R0, T& R1, T& R2,
+                                           T& RE) {
+        const T ud = d == 0 ? s.u0 : (d == 1 ? s.u1 : s.u2);
+        const T e0 = d2U0 + c0 * s.u0;
+        const T e1 = d2U1 + c0 * s.u1;
+        const T e2 = d2U2 + c0 * s.u2;
+        const T eT = d2T + c0 * s.Tm;
+        const T dMd = d == 0 ? dM0 : (d == 1 ? dM1 : dM2);
+        Rr -= T(0.5) * (dMd + ud * dRho + s.rho * dU);
+        R0 += c.inv_Re * e0 - T(0.5) * (dF0 + ud * dM0 + s.m0 * dU);
+        R1 += c.inv_Re * e1 - T(0.5) * (dF1 + ud * dM1 + s.m1 * dU);
+        R2 += c.inv_Re * e2 - T(0.5) * (dF2 + ud * dM2 + s.m2 * dU);
+        const T ed = d == 0 ? e0 : (d == 1 ? e1 : e2);
+        const T extra = c.inv_3Re * (ed + dTh);
+        if (d == 0) R0 += extra;
+        if (d == 1) R1 += extra;
+        if (d == 2) R2 += extra;
+        RE += c.kappa * eT - T(0.5) * (dH + ud * dE + s.E * dU);
+    }
+};
+
+// One workgroup = one (x, y) tile and one z-chunk [z0, z0 + zc).
+template <typename T, int R, int TX, int TY, int MODE>
+__device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
+                                                 const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
+                                                 T B) {
+    using S = FusedShape<R, TX, TY>;
+    __shared__ T s_u[3][S::BY2][S::BX2];
+    __shared__ T s_pl[kPlFields][S::BY1][S::BX1];
+
+    const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+    const int64_t P = c.P;
+    const int64_t plane = (int64_t)nx * ny;
+    const int tid = threadIdx.x;
+
+    // ---- column role and coordinates ----
+    int cx = 0, cy = 0;
+    const bool e1 = tid < S::NE1;
+    const bool interior = tid < S::NI;
+    if (tid < S::NI) {
+        cx = tid % TX;
+        cy = tid / TX;
+    } else if (tid < S::NI + S::NHX) {
+        const int t = tid - S::NI;
+        const int side = t / (R * TY);
+        const int t2 = t % (R * TY);
+        cy = t2 / R;
+        const int k = t2 % R;
+        cx = side ? TX + k : -R + k;
+    } else if (tid < S::NE1) {
+        const int t = tid - S::NI - S::NHX;
+        const int side = t / (R * TX);
+        const int t2 = t % (R * TX);
+        const int k = t2 / TX;
+        cx = t2 % TX;
+        cy = side ? TY + k : -R + k;
+    }
+    const int64_t col = (int64_t)wrap_mod(y0 + cy, ny) * nx + wrap_mod(x0 + cx, nx);
+    const bool store = interior && (x0 + cx < nx) && (y0 + cy < ny);
+
+    // u-only ring point of this thread (if any): E2 minus E1.
+    int ox = 0, oy = 0;
+    const bool has_out = tid < S::NOUT;
+    if (has_out) {
+        int t = tid;
+        if (t < 2 * R * TY) {                       // left / right, interior rows
+            const int side = t / (R * TY);
+            const int t2 = t % (R * TY);
+            oy = t2 / R;
+            const int k = t2 % R;
+            ox = side ? TX + R + k : -2 * R + k;
+        } else if ((t -= 2 * R * TY) < 2 * R * TX) {  // bottom / top, interior columns
+            const int side = t / (R * TX);
+            const int t2 = t % (R * TX);
+            const int k = t2 / TX;
+            ox = t2 % TX;
+            oy = side ? TY + R + k : -2 * R + k;
+        } else {                                    // the four R x R corners
+            t -= 2 * R * TX;
+            const int corner = t / (R * R);
+            const int t2 = t % (R * R);
+            const int ky = t2 / R, kx = t2 % R;
+            ox = (corner & 1) ? TX + kx : -R + kx;
+            oy = (corner & 2) ? TY + ky : -R + ky;
+        }
+    }
+    const int64_t ocol = (int64_t)wrap_mod(y0 + oy, ny) * nx + wrap_mod(x0 + ox, nx);
+
+    // ---- register windows ----
+    PF<T> Qb[3 * R + 1];          // point fields, planes L-3R .. L (index 3R = newest)
+    T Vz[2 * R + 1], Thz[2 * R + 1];  // z-direction nested fields, planes a-2R .. a
+    T Vx[R + 1], Thx[R + 1], Vy[R + 1], Thy[R + 1];  // planes a-R .. a
+#pragma unroll
+    for (int s = 0; s <= 3 * R; ++s) Qb[s] = PF<T>{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s <= 2 * R; ++s) Vz[s] = Thz[s] = 0;
+#pragma unroll
+    for (int s = 0; s <= R; ++s) Vx[s] = Thx[s] = Vy[s] = Thy[s] = 0;
+
+    const int iters = zc + 4 * R;
+    for (int it = 0; it < iters; ++it) {
+        const int L = z0 - 2 * R + it;           // plane loaded this iteration
+        // 1. load plane L into the window
+        if (e1) {
+            const int64_t idx = (int64_t)wrap_mod(L, nz) * plane + col;
+            const PF<T> f = make_pf<T>(q[idx], q[P + idx], q[2 * P + idx], q[3 * P + idx], q[4 * P + idx], c.gm1, c.gM2);
+#pragma unroll
+            for (int s = 0; s < 3 * R; ++s) Qb[s] = Qb[s + 1];
+            Qb[3 * R] = f;
+        }
+        const bool do_grad = it >= 2 * R;
+        const bool do_out = it >= 4 * R;
+        // 2. LDS plane of u at the gradient plane a = L - R
+        if (do_grad) {
+            if (e1) {
+                s_u[0][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u0;
+                s_u[1][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u1;
+                s_u[2][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u2;
+            }
+            if (has_out) {
+                const int64_t idx = (int64_t)wrap_mod(L - R, nz) * plane + ocol;
+                const T rr = T(1) / q[idx];
+                s_u[0][oy + 2 * R][ox + 2 * R] = q[P + idx] * rr;
+                s_u[1][oy + 2 * R][ox + 2 * R] = q[2 * P + idx] * rr;
+                s_u[2][oy + 2 * R][ox + 2 * R] = q[3 * P + idx] * rr;
+            }
+        }
+        __syncthreads();
+        // 3. velocity gradient at plane a -> nested fields; LDS plane of point fields at o
+        if (do_grad && e1) {
+            T g[3][3];
+#pragma unroll
+            for (int b = 0; b < 3; ++b) {
+                T sx = 0, sy = 0, sz = 0;
+#pragma unroll
+                for (int m = 1; m <= R; ++m) {
+                    sx += c.da[0][m - 1] * (s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m]);
+                    sy += c.da[1][m - 1] * (s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R]);
+                    const T up = b == 0 ? Qb[2 * R + m].u0 : (b == 1 ? Qb[2 * R + m].u1 : Qb[2 * R + m].u2);
+                    const T um = b == 0 ? Qb[2 * R - m].u0 : (b == 1 ? Qb[2 * R - m].u1 : Qb[2 * R - m].u2);
+                    sz += c.da[2][m - 1] * (up - um);
+                }
+                g[b][0] = sx;
+                g[b][1] = sy;
+                g[b][2] = sz;
+            }
+            const T uc[3] = {Qb[2 * R].u0, Qb[2 * R].u1, Qb[2 * R].u2};
+            const T theta = g[0][0] + g[1][1] + g[2][2];
+            T V[3];
+#pragma unroll
+            for (int jj = 0; jj < 3; ++jj) {
+                T v = 0;
+#pragma unroll
+                for (int ii = 0; ii < 3; ++ii) {
+                    T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
+                    if (ii == jj) tau -= c.inv_Re23 * theta;
+                    v += uc[ii] * tau;
+                }
+                V[jj] = v;
+            }
+#pragma unroll
+            for (int s = 0; s < 2 * R; ++s) { Vz[s] = Vz[s + 1]; Thz[s] = Thz[s + 1]; }
+            Vz[2 * R] = V[2];
+            Thz[2 * R] = theta - g[2][2];
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                Vx[s] = Vx[s + 1]; Thx[s] = Thx[s + 1];
+                Vy[s] = Vy[s + 1]; Thy[s] = Thy[s + 1];
+            }
+            Vx[R] = V[0];
+            Thx[R] = theta - g[0][0];
+            Vy[R] = V[1];
+            Thy[R] = theta - g[1][1];
+        }
+        if (do_out && e1) {
+            const PF<T>& f = Qb[R];
+            const int ly = cy + R, lx = cx + R;
+            s_pl[0][ly][lx] = f.rho;
+            s_pl[1][ly][lx] = f.m0;
+            s_pl[2][ly][lx] = f.m1;
+            s_pl[3][ly][lx] = f.m2;
+            s_pl[4][ly][lx] = f.E;
+            s_pl[5][ly][lx] = f.u0;
+            s_pl[6][ly][lx] = f.u1;
+            s_pl[7][ly][lx] = f.u2;
+            s_pl[8][ly][lx] = f.p;
+            s_pl[9][ly][lx] = f.Tm;
+            s_pl[10][ly][lx] = Vx[0];
+            s_pl[11][ly][lx] = Thx[0];
+            s_pl[12][ly][lx] = Vy[0];
+            s_pl[13][ly][lx] = Thy[0];
+        }
+        __syncthreads();
+        // 4. residual and RK update at the output plane o = L - 2R
+        if (do_out && interior) {
+            const int ly = cy + R, lx = cx + R;
+            auto ld = [&](int yy, int xx) {
+                PF<T> f;
+                f.rho = s_pl[0][yy][xx];
+                f.m0 = s_pl[1][yy][xx];
+                f.m1 = s_pl[2][yy][xx];
+                f.m2 = s_pl[3][yy][xx];
+                f.E = s_pl[4][yy][xx];
+                f.u0 = s_pl[5][yy][xx];
+                f.u1 = s_pl[6][yy][xx];
+                f.u2 = s_pl[7][yy][xx];
+                f.p = s_pl[8][yy][xx];
+                f.Tm = s_pl[9][yy][xx];
+                return f;
+            };
+            const PF<T>& s = Qb[R];
+            T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
+            {
+                DirSums<T> ds;
+                ds.zero();
+#pragma unroll
+                for (int m = 1; m <= R; ++m)
+                    ds.template add<0>(ld(ly, lx + m), s_pl[10][ly][lx + m], s_pl[11][ly][lx + m], ld(ly, lx - m),
+                                       s_pl[10][ly][lx - m], s_pl[11][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
+                ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
+            }
+            {
+                DirSums<T> ds;
+                ds.zero();
+#pragma unroll
+                for (int m = 1; m <= R; ++m)
+                    ds.template add<1>(ld(ly + m, lx), s_pl[12][ly + m][lx], s_pl[13][ly + m][lx], ld(ly - m, lx),
+                                       s_pl[12][ly - m][lx], s_pl[13][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
+                ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
+            }
+            {
+                DirSums<T> ds;
+                ds.zero();
+#pragma unroll
+                for (int m = 1; m <= R; ++m)
+                    ds.template add<2>(Qb[R + m], Vz[R + m], Thz[R + m], Qb[R - m], Vz[R - m], Thz[R - m],
+                                       c.da[2][m - 1], c.d2c[2][m - 1]);
+                ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
+            }
+            if (store) {
+                const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+                const T Rv[5] = {Rr, R0, R1, R2, RE};
+                const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
+#pragma unroll
+                for (int f = 0; f < 5; ++f) {
+                    if (MODE == kModeRHS) {
+                        out[f * P + idx] = Rv[f];
+                    } else {
+                        T dn = dt * Rv[f];
+                        if (MODE != kModeStage1) dn += A * dq[f * P + idx];
+                        if (MODE != kModeStage3) dq[f * P + idx] = dn;
+                        out[f * P + idx] = qv[f] + B * dn;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Single-box launch: blockIdx.x enumerates (x, y) tiles, blockIdx.y z-chunks.
+template <typename T, int R, int TX, int TY, int MODE>
+__global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
+    fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out, BoxConst<T> c, int zchunk,
+                       T dt, T A, T B) {
+    const int tiles_x = (c.n[0] + TX - 1) / TX;
+    const int tx = blockIdx.x % tiles_x;
+    const int ty = blockIdx.x / tiles_x;
+    const int z0 = blockIdx.y * zchunk;
+    const int zc = min(zchunk, c.n[2] - z0);
+    fused_stage_body<T, R, TX, TY, MODE>(q, dq, out, c, tx * TX, ty * TY, z0, zc, dt, A, B);
+}
+
+}  // namespace sbli

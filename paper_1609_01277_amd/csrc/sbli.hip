@@ -10,7 +10,7 @@
 
 #include "../../include/sbli.h"
 #include "kernels_pointwise.h"
-#include "kernels_stage_simple.h"
+#include "kernels_stage_fused.h"
 #include "stencil_weights.h"
 
 using namespace sbli;
@@ -24,7 +24,7 @@ struct sbli_ctx {
     double a[kMaxR], c0, c[kMaxR];
     BoxConst<double> c64;
     BoxConst<float> c32;
-    void* W;                // nested-derivative fields, 6 * P elements of the state type
+    int zchunk;             // z-planes per workgroup of the fused stage kernel
     double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
     double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
     double* diag_out;       // 10 doubles
@@ -72,6 +72,16 @@ static void fill_const(const sbli_ctx* x, BoxConst<T>& c) {
     c.kappa = (T)(1.0 / ((g - 1.0) * M * M * x->p.Pr * x->p.Re));
 }
 
+// z-planes per workgroup: long enough to amortise the 4R-plane pipeline fill,
+// short enough to give the 256 compute units several workgroups each.
+static int default_zchunk(const sbli_ctx* x) {
+    const int tx = 16, ty = 16;
+    const long tiles = (long)((x->p.nx + tx - 1) / tx) * ((x->p.ny + ty - 1) / ty);
+    int zc = x->p.nz;
+    while (zc > 32 && tiles * ((x->p.nz + zc - 1) / zc) < 2048) zc = (zc + 1) / 2;
+    return zc;
+}
+
 static size_t elem_size(const sbli_ctx* x) { return x->p.dtype == SBLI_F32 ? sizeof(float) : sizeof(double); }
 static int64_t npoints(const sbli_ctx* x) { return (int64_t)x->p.nx * x->p.ny * x->p.nz; }
 
@@ -114,9 +124,8 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     fill_const(x, x->c64);
     fill_const(x, x->c32);
 
+    x->zchunk = default_zchunk(x);
     hipError_t e = hipGetDevice(&x->device);
-    const size_t wbytes = 6 * (size_t)npoints(x) * elem_size(x);
-    if (e == hipSuccess) e = hipMalloc(&x->W, wbytes);
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_part, sizeof(double) * kDiagBlocks * (2 * kDiagQ + 3));
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_da, sizeof(double) * 3 * kMaxR);
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_out, sizeof(double) * 10);
@@ -130,7 +139,6 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     if (e != hipSuccess) {
         int code = (e == hipErrorOutOfMemory) ? SBLI_ERR_ALLOC : SBLI_ERR_HIP;
         fail(nullptr, code, "sbli_init: %s", hipGetErrorString(e));
-        hipFree(x->W);
         hipFree(x->diag_part);
         hipFree(x->diag_da);
         hipFree(x->diag_out);
@@ -144,7 +152,6 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
 extern "C" int sbli_destroy(sbli_ctx* ctx) {
     if (!ctx) return SBLI_OK;
     hipStreamSynchronize(ctx->stream);
-    hipFree(ctx->W);
     hipFree(ctx->diag_part);
     hipFree(ctx->diag_da);
     hipFree(ctx->diag_out);
@@ -174,16 +181,31 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
     return SBLI_OK;
 }
 
+// Tile shape of the fused stage kernel per (type, radius): interior columns
+// fill whole wavefronts and the register windows fit the occupancy target.
+template <typename T, int R>
+struct TileCfg {
+    static constexpr int TX = 16;
+    static constexpr int TY = (R <= 2 || (sizeof(T) == 4 && R == 3)) ? 16 : (sizeof(T) == 8 && R == 4 ? 4 : 8);
+};
+
+template <typename T, int R, int MODE>
+static void launch_fused(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, T dt, T A, T B) {
+    constexpr int TX = TileCfg<T, R>::TX, TY = TileCfg<T, R>::TY;
+    const int tiles = ((c.n[0] + TX - 1) / TX) * ((c.n[1] + TY - 1) / TY);
+    const int chunks = (c.n[2] + ctx->zchunk - 1) / ctx->zchunk;
+    dim3 grid(tiles, chunks);
+    fused_stage_kernel<T, R, TX, TY, MODE><<<grid, FusedShape<R, TX, TY>::NT, 0, ctx->stream>>>(qin, dq, qout, c,
+                                                                                            ctx->zchunk, dt, A, B);
+}
+
 template <typename T, int R>
 static void launch_stage(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, int mode, T dt, T A, T B) {
-    const unsigned blocks = (unsigned)((c.P + 255) / 256);
-    T* W = (T*)ctx->W;
-    grad_kernel<T, R><<<blocks, 256, 0, ctx->stream>>>(qin, W, c);
     switch (mode) {
-        case kModeRHS: stage_kernel<T, R, kModeRHS><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
-        case kModeStage1: stage_kernel<T, R, kModeStage1><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
-        case kModeStage2: stage_kernel<T, R, kModeStage2><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
-        default: stage_kernel<T, R, kModeStage3><<<blocks, 256, 0, ctx->stream>>>(qin, W, dq, qout, c, dt, A, B); break;
+        case kModeRHS: launch_fused<T, R, kModeRHS>(ctx, c, qin, dq, qout, dt, A, B); break;
+        case kModeStage1: launch_fused<T, R, kModeStage1>(ctx, c, qin, dq, qout, dt, A, B); break;
+        case kModeStage2: launch_fused<T, R, kModeStage2>(ctx, c, qin, dq, qout, dt, A, B); break;
+        default: launch_fused<T, R, kModeStage3>(ctx, c, qin, dq, qout, dt, A, B); break;
     }
 }
 

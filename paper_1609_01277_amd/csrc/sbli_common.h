@@ -26,6 +26,8 @@ struct BoxConst {
     T inv_Re23;               // 2 / (3 Re)
 };
 
+enum StageMode { kModeRHS = 0, kModeStage1 = 1, kModeStage2 = 2, kModeStage3 = 3 };
+
 // Index of the neighbour `m` points away along `axis` (periodic), given the
 // point's coordinate `c` on that axis, its linear index `id` and the axis
 // stride.  Requires |m| < n.
