@@ -31,6 +31,7 @@ def measure(sbli, torch, n, order, dtype, steps, warmup):
     """Time `steps` RK3 steps after `warmup`; returns a dict of results."""
     import synth
     s = sbli.Solver(n, order=order, dtype=dtype, **synth.TGV)
+    tune = s.autotune(reps=2)
     q, qt, dq = s.empty_state(), s.empty_state(), s.empty_state()
     s.tgv_init(q)
     dt = synth.tgv_dt(n)
@@ -59,7 +60,7 @@ def measure(sbli, torch, n, order, dtype, steps, warmup):
                 value=P * steps / (ms * 1e-3) / 1e6, avg_launch_ms=avg_launch_ms,
                 bytes_per_launch=bytes_per_launch, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, diag_status=code, Ek=diag["Ek"],
-                enstrophy=diag["enstrophy"])
+                enstrophy=diag["enstrophy"], tuning=tune)
 
 
 def cpu_baseline(n=256, order=4):
@@ -88,6 +89,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and order-8 lines")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=256)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -101,6 +104,17 @@ def main():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give the
+        # factor between counted and true HBM bytes.
+        n = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d MiB x 5" % args.calibrate_copy)
+        return
     from paper_1609_01277_amd import _lib
     if not os.path.exists(_lib.LIB_PATH):
         import __graft_entry__
@@ -120,7 +134,7 @@ def main():
                 continue
             r = measure(sbli, torch, args.n, order, dt_, args.steps, args.warmup)
             key = "%s_order%d" % (dt_, order)
-            extra[key] = {k: r[k] for k in ("value", "ms_per_step", "achieved_gbs", "frac")}
+            extra[key] = {k: r[k] for k in ("value", "ms_per_step", "achieved_gbs", "frac", "tuning")}
             log("extra %s: %.1f Mpt-steps/s, %.0f GB/s (%.1f%%)" % (key, r["value"], r["achieved_gbs"],
                                                                     100 * r["frac"]))
 
@@ -152,7 +166,8 @@ def main():
                      "kernel": "RK3 stage (residual + update), all launches of the timed region",
                      "algorithmic_bytes_per_launch": main_r["bytes_per_launch"],
                      "avg_launch_ms": main_r["avg_launch_ms"],
-                     "words_per_point_step": WORDS_PER_POINT_STEP, "word_bytes": word},
+                     "words_per_point_step": WORDS_PER_POINT_STEP, "word_bytes": word,
+                     "launch": main_r["tuning"]},
         "cpu_baseline": cpu,
         "extra": extra,
         "diagnostics_after_run": {"Ek": main_r["Ek"], "enstrophy": main_r["enstrophy"],

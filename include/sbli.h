@@ -124,6 +124,29 @@ int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int 
  */
 int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
 
+/*
+ * Launch tuning of the fused stage kernel.  Each (dtype, order) has a small set
+ * of compiled variants (x/y tile of a workgroup and how far the global loads
+ * run ahead); together with the number of z-planes per workgroup ("zchunk") they
+ * fix the launch configuration.  All variants compute bitwise identical
+ * results; only speed differs.
+ *
+ * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
+ * sbli_variant_info: info = {tile x, tile y, load-ahead depth} of a variant.
+ * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
+ *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).
+ * sbli_autotune: time every variant with several zchunks (hipEvents on the
+ *   context's stream, `reps` RK3 steps each after one warm-up step) using the
+ *   caller's device buffers, then select the fastest; *best_ms (may be NULL)
+ *   receives its time per step.  The contents of q, q_tmp and dq afterwards are
+ *   unspecified (they are advanced in time).  Synchronises the stream.
+ */
+int sbli_num_variants(const sbli_ctx* ctx);
+int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]);
+int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk);
+int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk);
+int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -7,14 +7,17 @@ class that uses PyTorch only to allocate device memory and to pick the stream.
 """
 import math
 
-from . import _lib
+from . import _lib, tuning
 from ._lib import (SBLI_ERR_ALLOC, SBLI_ERR_ARG, SBLI_ERR_HIP, SBLI_ERR_NONFINITE,  # noqa: F401
                    SBLI_ERR_UNSUPPORTED, SBLI_F32, SBLI_F64, SBLI_OK, SbliError, sbli_destroy,
                    sbli_diagnostics, sbli_init, sbli_last_error, sbli_params, sbli_rhs,
-                   sbli_rk3_step, sbli_tgv_init)
+                   sbli_rk3_step, sbli_tgv_init, sbli_num_variants, sbli_variant_info,
+                   sbli_set_tuning, sbli_get_tuning, sbli_autotune)
 
 __all__ = ["Solver", "make_params", "SbliError", "sbli_init", "sbli_destroy", "sbli_last_error",
-           "sbli_tgv_init", "sbli_rhs", "sbli_rk3_step", "sbli_diagnostics", "sbli_params"]
+           "sbli_tgv_init", "sbli_rhs", "sbli_rk3_step", "sbli_diagnostics", "sbli_params",
+           "sbli_num_variants", "sbli_variant_info", "sbli_set_tuning", "sbli_get_tuning",
+           "sbli_autotune"]
 
 DIAG_NAMES = ("Ek", "enstrophy", "rho", "rhou", "rhov", "rhow", "rhoE")
 
@@ -92,3 +95,17 @@ class Solver:
         self._check_state(q, "q")
         vals, code = sbli_diagnostics(self.ctx, q, check=check)
         return dict(zip(DIAG_NAMES, vals)), code
+
+    # ---- launch tuning ----
+    def variants(self):
+        return [sbli_variant_info(self.ctx, v) for v in range(sbli_num_variants(self.ctx))]
+
+    def set_tuning(self, variant, zchunk):
+        sbli_set_tuning(self.ctx, variant, zchunk)
+
+    def get_tuning(self):
+        return sbli_get_tuning(self.ctx)
+
+    def autotune(self, reps=2, force=False, path=None):
+        kw = {} if path is None else {"path": path}
+        return tuning.autotune(self, reps=reps, force=force, **kw)

@@ -55,8 +55,16 @@ def load():
     lib.sbli_rhs.argtypes = [vp, vp, vp]
     lib.sbli_rk3_step.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_int]
     lib.sbli_diagnostics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+    ip = ctypes.POINTER(ctypes.c_int)
+    lib.sbli_num_variants.argtypes = [vp]
+    lib.sbli_variant_info.argtypes = [vp, ctypes.c_int, ip]
+    lib.sbli_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    lib.sbli_get_tuning.argtypes = [vp, ip, ip]
+    lib.sbli_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_double, ctypes.c_int,
+                                  ctypes.POINTER(ctypes.c_double)]
     for name in ("sbli_init", "sbli_destroy", "sbli_tgv_init", "sbli_rhs", "sbli_rk3_step",
-                 "sbli_diagnostics"):
+                 "sbli_diagnostics", "sbli_num_variants", "sbli_variant_info", "sbli_set_tuning",
+                 "sbli_get_tuning", "sbli_autotune"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -116,3 +124,33 @@ def sbli_diagnostics(ctx, q, check=True):
     if code not in (SBLI_OK, SBLI_ERR_NONFINITE) or (check and code != SBLI_OK):
         _check(code, ctx)
     return list(out), code
+
+
+def sbli_num_variants(ctx):
+    n = load().sbli_num_variants(ctx)
+    if n < 0:
+        _check(n, ctx)
+    return n
+
+
+def sbli_variant_info(ctx, variant):
+    info = (ctypes.c_int * 3)()
+    _check(load().sbli_variant_info(ctx, int(variant), info), ctx)
+    return tuple(info)
+
+
+def sbli_set_tuning(ctx, variant, zchunk):
+    return _check(load().sbli_set_tuning(ctx, int(variant), int(zchunk)), ctx)
+
+
+def sbli_get_tuning(ctx):
+    v, z = ctypes.c_int(), ctypes.c_int()
+    _check(load().sbli_get_tuning(ctx, ctypes.byref(v), ctypes.byref(z)), ctx)
+    return v.value, z.value
+
+
+def sbli_autotune(ctx, q, q_tmp, dq, dt, reps=2):
+    ms = ctypes.c_double()
+    _check(load().sbli_autotune(ctx, _ptr(q), _ptr(q_tmp), _ptr(dq), float(dt), int(reps),
+                                ctypes.byref(ms)), ctx)
+    return ms.value

@@ -70,8 +70,8 @@ __device__ __forceinline__ int wrap_mod(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Number of LDS fields of the output plane: 10 point fields + (V_x, Th_x, V_y, Th_y).
-constexpr int kPlFields = 14;
+// Number of LDS fields of the output plane (the point fields).
+constexpr int kPlFields = 10;
 
 // Accumulates, for one direction d, the derivative sums of the residual from a
 // neighbour pair (a = +m, b = -m) with weights w (first) and w2 (second).
@@ -134,13 +134,21 @@ struct DirSums {
 };
 
 // One workgroup = one (x, y) tile and one z-chunk [z0, z0 + zc).
-template <typename T, int R, int TX, int TY, int MODE>
+// PRE selects how far global loads run ahead of their use: 0 = loaded where used,
+// 1 = the state of the next plane and the next u-ring point are requested one
+// iteration early, 2 = dq of the next output plane as well.
+template <typename T, int R, int TX, int TY, int MODE, int PRE>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
                                                  T B) {
     using S = FusedShape<R, TX, TY>;
     __shared__ T s_u[3][S::BY2][S::BX2];
     __shared__ T s_pl[kPlFields][S::BY1][S::BX1];
+    // Rings of the nested-derivative fields, indexed by iteration: (V_x, Th_x,
+    // V_y, Th_y) of the last R+1 gradient planes over the tile and its R-ring,
+    // and (V_z, Th_z) of the last 2R+1 gradient planes over the tile.
+    __shared__ T s_axy[R + 1][4][S::BY1][S::BX1];
+    __shared__ T s_az[2 * R + 1][2][TY][TX];
 
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P;
@@ -202,22 +210,52 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
 
     // ---- register windows ----
     PF<T> Qb[3 * R + 1];          // point fields, planes L-3R .. L (index 3R = newest)
-    T Vz[2 * R + 1], Thz[2 * R + 1];  // z-direction nested fields, planes a-2R .. a
-    T Vx[R + 1], Thx[R + 1], Vy[R + 1], Thy[R + 1];  // planes a-R .. a
 #pragma unroll
     for (int s = 0; s <= 3 * R; ++s) Qb[s] = PF<T>{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-    for (int s = 0; s <= 2 * R; ++s) Vz[s] = Thz[s] = 0;
-#pragma unroll
-    for (int s = 0; s <= R; ++s) Vx[s] = Thx[s] = Vy[s] = Thy[s] = 0;
 
     const int iters = zc + 4 * R;
-    for (int it = 0; it < iters; ++it) {
-        const int L = z0 - 2 * R + it;           // plane loaded this iteration
-        // 1. load plane L into the window
+    // With PRE > 0 the loads of iteration it+1 are issued before the work of
+    // iteration it starts, and consumed one iteration later.
+    T pq0 = 0, pq1 = 0, pq2 = 0, pq3 = 0, pq4 = 0;   // next q (own column)
+    T pr0 = 1, pr1 = 0, pr2 = 0, pr3 = 0;            // next ring point (rho, rho u_i)
+    T pd0 = 0, pd1 = 0, pd2 = 0, pd3 = 0, pd4 = 0;   // next dq (own column)
+    auto issue = [&](int it) {
+        const int L = z0 - 2 * R + it;
         if (e1) {
             const int64_t idx = (int64_t)wrap_mod(L, nz) * plane + col;
-            const PF<T> f = make_pf<T>(q[idx], q[P + idx], q[2 * P + idx], q[3 * P + idx], q[4 * P + idx], c.gm1, c.gM2);
+            pq0 = q[idx];
+            pq1 = q[P + idx];
+            pq2 = q[2 * P + idx];
+            pq3 = q[3 * P + idx];
+            pq4 = q[4 * P + idx];
+        }
+        if (has_out && it >= 2 * R) {
+            const int64_t idx = (int64_t)wrap_mod(L - R, nz) * plane + ocol;
+            pr0 = q[idx];
+            pr1 = q[P + idx];
+            pr2 = q[2 * P + idx];
+            pr3 = q[3 * P + idx];
+        }
+        if (PRE == 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store && it >= 4 * R) {
+            const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+            pd0 = dq[idx];
+            pd1 = dq[P + idx];
+            pd2 = dq[2 * P + idx];
+            pd3 = dq[3 * P + idx];
+            pd4 = dq[4 * P + idx];
+        }
+    };
+    if (PRE > 0) issue(0);
+    for (int it = 0; it < iters; ++it) {
+        const int L = z0 - 2 * R + it;           // plane loaded this iteration
+        if (PRE == 0) issue(it);
+        const T cq0 = pq0, cq1 = pq1, cq2 = pq2, cq3 = pq3, cq4 = pq4;
+        const T cr0 = pr0, cr1 = pr1, cr2 = pr2, cr3 = pr3;
+        T cd[5] = {pd0, pd1, pd2, pd3, pd4};
+        if (PRE > 0 && it + 1 < iters) issue(it + 1);
+        // 1. plane L enters the window
+        if (e1) {
+            const PF<T> f = make_pf<T>(cq0, cq1, cq2, cq3, cq4, c.gm1, c.gM2);
 #pragma unroll
             for (int s = 0; s < 3 * R; ++s) Qb[s] = Qb[s + 1];
             Qb[3 * R] = f;
@@ -232,11 +270,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 s_u[2][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u2;
             }
             if (has_out) {
-                const int64_t idx = (int64_t)wrap_mod(L - R, nz) * plane + ocol;
-                const T rr = T(1) / q[idx];
-                s_u[0][oy + 2 * R][ox + 2 * R] = q[P + idx] * rr;
-                s_u[1][oy + 2 * R][ox + 2 * R] = q[2 * P + idx] * rr;
-                s_u[2][oy + 2 * R][ox + 2 * R] = q[3 * P + idx] * rr;
+                const T rr = T(1) / cr0;
+                s_u[0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
+                s_u[1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
+                s_u[2][oy + 2 * R][ox + 2 * R] = cr3 * rr;
             }
         }
         __syncthreads();
@@ -272,19 +309,16 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 }
                 V[jj] = v;
             }
-#pragma unroll
-            for (int s = 0; s < 2 * R; ++s) { Vz[s] = Vz[s + 1]; Thz[s] = Thz[s + 1]; }
-            Vz[2 * R] = V[2];
-            Thz[2 * R] = theta - g[2][2];
-#pragma unroll
-            for (int s = 0; s < R; ++s) {
-                Vx[s] = Vx[s + 1]; Thx[s] = Thx[s + 1];
-                Vy[s] = Vy[s + 1]; Thy[s] = Thy[s + 1];
+            const int sxy = it % (R + 1);
+            s_axy[sxy][0][cy + R][cx + R] = V[0];
+            s_axy[sxy][1][cy + R][cx + R] = theta - g[0][0];
+            s_axy[sxy][2][cy + R][cx + R] = V[1];
+            s_axy[sxy][3][cy + R][cx + R] = theta - g[1][1];
+            if (interior) {
+                const int sz = it % (2 * R + 1);
+                s_az[sz][0][cy][cx] = V[2];
+                s_az[sz][1][cy][cx] = theta - g[2][2];
             }
-            Vx[R] = V[0];
-            Thx[R] = theta - g[0][0];
-            Vy[R] = V[1];
-            Thy[R] = theta - g[1][1];
         }
         if (do_out && e1) {
             const PF<T>& f = Qb[R];
@@ -299,15 +333,16 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             s_pl[7][ly][lx] = f.u2;
             s_pl[8][ly][lx] = f.p;
             s_pl[9][ly][lx] = f.Tm;
-            s_pl[10][ly][lx] = Vx[0];
-            s_pl[11][ly][lx] = Thx[0];
-            s_pl[12][ly][lx] = Vy[0];
-            s_pl[13][ly][lx] = Thy[0];
         }
         __syncthreads();
         // 4. residual and RK update at the output plane o = L - 2R
         if (do_out && interior) {
             const int ly = cy + R, lx = cx + R;
+            if (PRE < 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store) {
+                const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+#pragma unroll
+                for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
+            }
             auto ld = [&](int yy, int xx) {
                 PF<T> f;
                 f.rho = s_pl[0][yy][xx];
@@ -323,14 +358,15 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 return f;
             };
             const PF<T>& s = Qb[R];
+            auto& axy = s_axy[(it - R) % (R + 1)];   // nested fields of plane o
             T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
             {
                 DirSums<T> ds;
                 ds.zero();
 #pragma unroll
                 for (int m = 1; m <= R; ++m)
-                    ds.template add<0>(ld(ly, lx + m), s_pl[10][ly][lx + m], s_pl[11][ly][lx + m], ld(ly, lx - m),
-                                       s_pl[10][ly][lx - m], s_pl[11][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
+                    ds.template add<0>(ld(ly, lx + m), axy[0][ly][lx + m], axy[1][ly][lx + m], ld(ly, lx - m),
+                                       axy[0][ly][lx - m], axy[1][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
                 ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
             }
             {
@@ -338,8 +374,8 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 ds.zero();
 #pragma unroll
                 for (int m = 1; m <= R; ++m)
-                    ds.template add<1>(ld(ly + m, lx), s_pl[12][ly + m][lx], s_pl[13][ly + m][lx], ld(ly - m, lx),
-                                       s_pl[12][ly - m][lx], s_pl[13][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
+                    ds.template add<1>(ld(ly + m, lx), axy[2][ly + m][lx], axy[3][ly + m][lx], ld(ly - m, lx),
+                                       axy[2][ly - m][lx], axy[3][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
                 ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
             }
             {
@@ -347,7 +383,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 ds.zero();
 #pragma unroll
                 for (int m = 1; m <= R; ++m)
-                    ds.template add<2>(Qb[R + m], Vz[R + m], Thz[R + m], Qb[R - m], Vz[R - m], Thz[R - m],
+                    ds.template add<2>(Qb[R + m], s_az[(it + m - R) % (2 * R + 1)][0][cy][cx],
+                                       s_az[(it + m - R) % (2 * R + 1)][1][cy][cx], Qb[R - m],
+                                       s_az[(it - m - R) % (2 * R + 1)][0][cy][cx],
+                                       s_az[(it - m - R) % (2 * R + 1)][1][cy][cx],
                                        c.da[2][m - 1], c.d2c[2][m - 1]);
                 ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
             }
@@ -361,7 +400,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                         out[f * P + idx] = Rv[f];
                     } else {
                         T dn = dt * Rv[f];
-                        if (MODE != kModeStage1) dn += A * dq[f * P + idx];
+                        if (MODE != kModeStage1) dn += A * cd[f];
                         if (MODE != kModeStage3) dq[f * P + idx] = dn;
                         out[f * P + idx] = qv[f] + B * dn;
                     }
@@ -371,17 +410,26 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     }
 }
 
-// Single-box launch: blockIdx.x enumerates (x, y) tiles, blockIdx.y z-chunks.
-template <typename T, int R, int TX, int TY, int MODE>
+// Single-box launch over a 1D grid of tiles x z-chunks.  Workgroups are handed
+// to the 8 XCDs round-robin by id; the id is remapped so that each XCD (with
+// its own L2) walks a contiguous run of neighbouring tiles, whose halos then
+// hit in that L2.
+template <typename T, int R, int TX, int TY, int MODE, int PRE>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out, BoxConst<T> c, int zchunk,
                        T dt, T A, T B) {
     const int tiles_x = (c.n[0] + TX - 1) / TX;
-    const int tx = blockIdx.x % tiles_x;
-    const int ty = blockIdx.x / tiles_x;
-    const int z0 = blockIdx.y * zchunk;
+    const int tiles_y = (c.n[1] + TY - 1) / TY;
+    const int total = gridDim.x;
+    const int w = blockIdx.x;
+    const int lam = (total % 8 == 0) ? (w % 8) * (total / 8) + w / 8 : w;
+    const int tile = lam % (tiles_x * tiles_y);
+    const int chunk = lam / (tiles_x * tiles_y);
+    const int tx = tile % tiles_x;
+    const int ty = tile / tiles_x;
+    const int z0 = chunk * zchunk;
     const int zc = min(zchunk, c.n[2] - z0);
-    fused_stage_body<T, R, TX, TY, MODE>(q, dq, out, c, tx * TX, ty * TY, z0, zc, dt, A, B);
+    fused_stage_body<T, R, TX, TY, MODE, PRE>(q, dq, out, c, tx * TX, ty * TY, z0, zc, dt, A, B);
 }
 
 }  // namespace sbli

@@ -10,7 +10,7 @@
 
 #include "../../include/sbli.h"
 #include "kernels_pointwise.h"
-#include "kernels_stage_fused.h"
+#include "stage_variants.h"
 #include "stencil_weights.h"
 
 using namespace sbli;
@@ -25,6 +25,7 @@ struct sbli_ctx {
     BoxConst<double> c64;
     BoxConst<float> c32;
     int zchunk;             // z-planes per workgroup of the fused stage kernel
+    int variant;            // index into the compiled stage variants of (dtype, order)
     double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
     double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
     double* diag_out;       // 10 doubles
@@ -125,6 +126,7 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     fill_const(x, x->c32);
 
     x->zchunk = default_zchunk(x);
+    x->variant = 0;
     hipError_t e = hipGetDevice(&x->device);
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_part, sizeof(double) * kDiagBlocks * (2 * kDiagQ + 3));
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_da, sizeof(double) * 3 * kMaxR);
@@ -181,50 +183,16 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
     return SBLI_OK;
 }
 
-// Tile shape of the fused stage kernel per (type, radius): interior columns
-// fill whole wavefronts and the register windows fit the occupancy target.
-template <typename T, int R>
-struct TileCfg {
-    static constexpr int TX = 16;
-    static constexpr int TY = (R <= 2 || (sizeof(T) == 4 && R == 3)) ? 16 : (sizeof(T) == 8 && R == 4 ? 4 : 8);
-};
-
-template <typename T, int R, int MODE>
-static void launch_fused(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, T dt, T A, T B) {
-    constexpr int TX = TileCfg<T, R>::TX, TY = TileCfg<T, R>::TY;
-    const int tiles = ((c.n[0] + TX - 1) / TX) * ((c.n[1] + TY - 1) / TY);
-    const int chunks = (c.n[2] + ctx->zchunk - 1) / ctx->zchunk;
-    dim3 grid(tiles, chunks);
-    fused_stage_kernel<T, R, TX, TY, MODE><<<grid, FusedShape<R, TX, TY>::NT, 0, ctx->stream>>>(qin, dq, qout, c,
-                                                                                            ctx->zchunk, dt, A, B);
-}
-
-template <typename T, int R>
-static void launch_stage(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, int mode, T dt, T A, T B) {
-    switch (mode) {
-        case kModeRHS: launch_fused<T, R, kModeRHS>(ctx, c, qin, dq, qout, dt, A, B); break;
-        case kModeStage1: launch_fused<T, R, kModeStage1>(ctx, c, qin, dq, qout, dt, A, B); break;
-        case kModeStage2: launch_fused<T, R, kModeStage2>(ctx, c, qin, dq, qout, dt, A, B); break;
-        default: launch_fused<T, R, kModeStage3>(ctx, c, qin, dq, qout, dt, A, B); break;
-    }
-}
-
-template <typename T>
-static void launch_stage_r(sbli_ctx* ctx, const BoxConst<T>& c, const T* qin, T* dq, T* qout, int mode, T dt, T A, T B) {
-    switch (ctx->r) {
-        case 1: launch_stage<T, 1>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
-        case 2: launch_stage<T, 2>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
-        case 3: launch_stage<T, 3>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
-        default: launch_stage<T, 4>(ctx, c, qin, dq, qout, mode, dt, A, B); break;
-    }
+static int num_variants(const sbli_ctx* ctx) {
+    return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::count(ctx->r) : StageDispatch<float>::count(ctx->r);
 }
 
 static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
+    const StageArgs a{ctx->stream, ctx->zchunk, mode, dt, A, B};
     if (ctx->p.dtype == SBLI_F64)
-        launch_stage_r<double>(ctx, ctx->c64, (const double*)qin, (double*)dq, (double*)qout, mode, dt, A, B);
+        StageDispatch<double>::launch(ctx->r, ctx->variant, a, ctx->c64, (const double*)qin, (double*)dq, (double*)qout);
     else
-        launch_stage_r<float>(ctx, ctx->c32, (const float*)qin, (float*)dq, (float*)qout, mode, (float)dt, (float)A,
-                              (float)B);
+        StageDispatch<float>::launch(ctx->r, ctx->variant, a, ctx->c32, (const float*)qin, (float*)dq, (float*)qout);
 }
 
 extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
@@ -241,16 +209,11 @@ extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
 static const double kRK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 static const double kRK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int nsteps) {
-    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_rk3_step: ctx is NULL");
-    if (!q || !q_tmp || !dq) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: NULL state pointer");
-    if (nsteps < 0) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: nsteps < 0");
-    if (!std::isfinite(dt)) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: dt is not finite");
-    const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
-    if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
-        return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: q, q_tmp and dq must not overlap");
-    void* src = q;
-    void* dst = q_tmp;
+// Enqueues nsteps RK3 steps ping-ponging between a and b; returns the buffer
+// that holds the result.
+static void* enqueue_steps(sbli_ctx* ctx, void* a, void* b, void* dq, double dt, int nsteps) {
+    void* src = a;
+    void* dst = b;
     for (int s = 0; s < nsteps; ++s) {
         for (int k = 0; k < 3; ++k) {
             launch_any(ctx, src, dq, dst, kModeStage1 + k, dt, kRK_A[k], kRK_B[k]);
@@ -259,6 +222,18 @@ extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
             dst = t;
         }
     }
+    return src;
+}
+
+extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int nsteps) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_rk3_step: ctx is NULL");
+    if (!q || !q_tmp || !dq) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: NULL state pointer");
+    if (nsteps < 0) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: nsteps < 0");
+    if (!std::isfinite(dt)) return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: dt is not finite");
+    const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
+    if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
+        return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: q, q_tmp and dq must not overlap");
+    void* src = enqueue_steps(ctx, q, q_tmp, dq, dt, nsteps);
     HIP_TRY(ctx, hipGetLastError());
     if (src != q) HIP_TRY(ctx, hipMemcpyAsync(q, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     return SBLI_OK;
@@ -291,5 +266,92 @@ extern "C" int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]) {
     if (res[7] > 0 || res[8] > 0 || res[9] > 0)
         return fail(ctx, SBLI_ERR_NONFINITE, "sbli_diagnostics: %.0f non-finite values, %.0f points with rho <= 0, %.0f with p <= 0",
                     res[7], res[8], res[9]);
+    return SBLI_OK;
+}
+
+extern "C" int sbli_num_variants(const sbli_ctx* ctx) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_num_variants: ctx is NULL");
+    return num_variants(ctx);
+}
+
+extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]) {
+    if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
+    if (variant < 0 || variant >= num_variants(ctx))
+        return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
+    const StageVariant v = ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::get(ctx->r, variant)
+                                                    : StageDispatch<float>::get(ctx->r, variant);
+    info[0] = v.tx;
+    info[1] = v.ty;
+    info[2] = v.pre;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_set_tuning: ctx is NULL");
+    if (variant < 0 || variant >= num_variants(ctx))
+        return fail(ctx, SBLI_ERR_ARG, "sbli_set_tuning: variant %d out of range [0, %d)", variant, num_variants(ctx));
+    if (zchunk < 1 || zchunk > ctx->p.nz)
+        return fail(ctx, SBLI_ERR_ARG, "sbli_set_tuning: zchunk %d out of range [1, %d]", zchunk, ctx->p.nz);
+    ctx->variant = variant;
+    ctx->zchunk = zchunk;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk) {
+    if (!ctx || !variant || !zchunk) return fail(nullptr, SBLI_ERR_ARG, "sbli_get_tuning: NULL argument");
+    *variant = ctx->variant;
+    *zchunk = ctx->zchunk;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_autotune: ctx is NULL");
+    if (!q || !q_tmp || !dq) return fail(ctx, SBLI_ERR_ARG, "sbli_autotune: NULL state pointer");
+    if (reps < 1) return fail(ctx, SBLI_ERR_ARG, "sbli_autotune: reps must be >= 1");
+    const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
+    if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
+        return fail(ctx, SBLI_ERR_ARG, "sbli_autotune: q, q_tmp and dq must not overlap");
+    const int nz = ctx->p.nz;
+    int cands[8], nc = 0;
+    for (int zc = nz; zc >= 16 && nc < 6; zc = (zc + 1) / 2) {
+        cands[nc++] = zc;
+        if (zc == 16) break;
+    }
+    if (nc == 0) cands[nc++] = nz;
+    hipEvent_t e0, e1;
+    HIP_TRY(ctx, hipEventCreate(&e0));
+    HIP_TRY(ctx, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bv = ctx->variant, bz = ctx->zchunk;
+    for (int v = 0; v < num_variants(ctx); ++v) {
+        for (int ci = 0; ci < nc; ++ci) {
+            ctx->variant = v;
+            ctx->zchunk = cands[ci];
+            enqueue_steps(ctx, q, q_tmp, dq, dt, 1);          // warm-up
+            hipEventRecord(e0, ctx->stream);
+            enqueue_steps(ctx, q, q_tmp, dq, dt, reps);
+            hipEventRecord(e1, ctx->stream);
+            hipError_t err = hipEventSynchronize(e1);
+            if (err != hipSuccess) {
+                hipEventDestroy(e0);
+                hipEventDestroy(e1);
+                ctx->variant = bv;
+                ctx->zchunk = bz;
+                return fail(ctx, SBLI_ERR_HIP, "sbli_autotune: %s", hipGetErrorString(err));
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bv = v;
+                bz = cands[ci];
+            }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    ctx->variant = bv;
+    ctx->zchunk = bz;
+    if (best_ms) *best_ms = best / reps;
     return SBLI_OK;
 }

@@ -1,0 +1,124 @@
+// Compiled launch variants of the fused stage kernel and their dispatch.
+//
+// A variant fixes the (x, y) tile of a workgroup and how far the global loads
+// run ahead (see fused_stage_body).  Every variant performs the same arithmetic
+// per point in the same order, so all of them give bitwise identical states;
+// they differ only in speed, which the autotuner measures.
+#pragma once
+
+#include "kernels_stage_fused.h"
+
+namespace sbli {
+
+struct StageVariant {
+    int tx, ty, pre;
+};
+
+// X-macro lists of (TX, TY, PRE) per (type, radius).  The first entry is the
+// default before tuning.
+#define SBLI_VARIANTS_D1(X) X(16, 16, 0) X(16, 16, 1) X(32, 8, 1)
+#define SBLI_VARIANTS_D2(X) X(16, 16, 0) X(16, 16, 1) X(16, 8, 0) X(16, 8, 1) X(32, 8, 0)
+#define SBLI_VARIANTS_D3(X) X(8, 8, 0) X(8, 8, 1) X(16, 8, 1)
+#define SBLI_VARIANTS_D4(X) X(16, 4, 0) X(16, 4, 1) X(8, 8, 0)
+#define SBLI_VARIANTS_F1(X) X(16, 16, 0) X(16, 16, 1) X(32, 8, 1)
+#define SBLI_VARIANTS_F2(X) X(16, 16, 1) X(16, 16, 0) X(16, 16, 2) X(32, 8, 1) X(16, 8, 1)
+#define SBLI_VARIANTS_F3(X) X(16, 16, 0) X(16, 16, 1) X(16, 8, 1)
+#define SBLI_VARIANTS_F4(X) X(16, 8, 0) X(16, 8, 1) X(16, 4, 1)
+
+struct StageArgs {
+    hipStream_t stream;
+    int zchunk;
+    int mode;
+    double dt, A, B;
+};
+
+template <typename T, int R, int TX, int TY, int PRE, int MODE>
+inline void launch_fused_cfg(const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
+    const int tiles = ((c.n[0] + TX - 1) / TX) * ((c.n[1] + TY - 1) / TY);
+    const int chunks = (c.n[2] + a.zchunk - 1) / a.zchunk;
+    fused_stage_kernel<T, R, TX, TY, MODE, PRE><<<dim3(tiles * chunks), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
+        qin, dq, qout, c, a.zchunk, (T)a.dt, (T)a.A, (T)a.B);
+}
+
+template <typename T, int R, int TX, int TY, int PRE>
+inline bool try_variant(int& k, int want, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
+    if (k++ != want) return false;
+    switch (a.mode) {
+        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, kModeRHS>(a, c, qin, dq, qout); break;
+        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage1>(a, c, qin, dq, qout); break;
+        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage2>(a, c, qin, dq, qout); break;
+        default: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage3>(a, c, qin, dq, qout); break;
+    }
+    return true;
+}
+
+#define SBLI_TRY(TX_, TY_, PRE_) \
+    if (try_variant<T, R, TX_, TY_, PRE_>(k, v, a, c, qin, dq, qout)) return true;
+#define SBLI_ENTRY(TX_, TY_, PRE_) StageVariant{TX_, TY_, PRE_},
+
+template <typename T, int R>
+struct VariantSet;
+
+#define SBLI_VARIANT_SET(TYPE, RR, LIST)                                                                  \
+    template <>                                                                                           \
+    struct VariantSet<TYPE, RR> {                                                                         \
+        using T = TYPE;                                                                                   \
+        static constexpr int R = RR;                                                                      \
+        static int count() {                                                                              \
+            static const StageVariant t[] = {LIST(SBLI_ENTRY)};                                          \
+            return (int)(sizeof(t) / sizeof(t[0]));                                                       \
+        }                                                                                                 \
+        static StageVariant get(int i) {                                                                  \
+            static const StageVariant t[] = {LIST(SBLI_ENTRY)};                                          \
+            return t[i];                                                                                  \
+        }                                                                                                 \
+        static bool launch(int v, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) { \
+            int k = 0;                                                                                    \
+            LIST(SBLI_TRY)                                                                                \
+            return false;                                                                                 \
+        }                                                                                                 \
+    };
+
+SBLI_VARIANT_SET(double, 1, SBLI_VARIANTS_D1)
+SBLI_VARIANT_SET(double, 2, SBLI_VARIANTS_D2)
+SBLI_VARIANT_SET(double, 3, SBLI_VARIANTS_D3)
+SBLI_VARIANT_SET(double, 4, SBLI_VARIANTS_D4)
+SBLI_VARIANT_SET(float, 1, SBLI_VARIANTS_F1)
+SBLI_VARIANT_SET(float, 2, SBLI_VARIANTS_F2)
+SBLI_VARIANT_SET(float, 3, SBLI_VARIANTS_F3)
+SBLI_VARIANT_SET(float, 4, SBLI_VARIANTS_F4)
+
+#undef SBLI_TRY
+#undef SBLI_ENTRY
+#undef SBLI_VARIANT_SET
+
+// Runtime dispatch over (radius, variant) for one element type.
+template <typename T>
+struct StageDispatch {
+    static int count(int r) {
+        switch (r) {
+            case 1: return VariantSet<T, 1>::count();
+            case 2: return VariantSet<T, 2>::count();
+            case 3: return VariantSet<T, 3>::count();
+            default: return VariantSet<T, 4>::count();
+        }
+    }
+    static StageVariant get(int r, int i) {
+        switch (r) {
+            case 1: return VariantSet<T, 1>::get(i);
+            case 2: return VariantSet<T, 2>::get(i);
+            case 3: return VariantSet<T, 3>::get(i);
+            default: return VariantSet<T, 4>::get(i);
+        }
+    }
+    static bool launch(int r, int v, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
+        switch (r) {
+            case 1: return VariantSet<T, 1>::launch(v, a, c, qin, dq, qout);
+            case 2: return VariantSet<T, 2>::launch(v, a, c, qin, dq, qout);
+            case 3: return VariantSet<T, 3>::launch(v, a, c, qin, dq, qout);
+            default: return VariantSet<T, 4>::launch(v, a, c, qin, dq, qout);
+        }
+    }
+};
+
+}  // namespace sbli
