@@ -63,6 +63,43 @@ def measure(sbli, torch, n, order, dtype, steps, warmup):
                 enstrophy=diag["enstrophy"], tuning=tune)
 
 
+def measure_batch(sbli, torch, steps):
+    """64-box FP32 ensemble (seed 1609): one hipGraph replay of `steps` steps vs the
+    same steps box by box (3 launches per box per step)."""
+    import synth
+    b = sbli.Batch(synth.batch_instances(), order=4, dtype="f32")
+    tune_ms = b.autotune(reps=2)
+    q, qt, dq = b.tgv_init(b.empty_state()), b.empty_state(), b.empty_state()
+    pts = b.points()
+    stream = torch.cuda.current_stream()
+    b.capture(q, qt, dq, steps)
+    b.launch()                      # warm-up replay
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.launch()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
+    b.step_sequential(q, qt, dq, 1)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step_sequential(q, qt, dq, steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1)
+    diags, code = b.diagnostics(q, check=False)
+    v, zmax = b.get_tuning()
+    del q, qt, dq
+    b.close()
+    torch.cuda.empty_cache()
+    return {"boxes": 64, "points": pts, "steps": steps,
+            "graph_value": pts * steps / (ms_graph * 1e-3) / 1e6,
+            "sequential_value": pts * steps / (ms_seq * 1e-3) / 1e6,
+            "speedup": ms_seq / ms_graph, "graph_ms": ms_graph, "sequential_ms": ms_seq,
+            "unit": "Mpoint-RK3-steps/s", "variant": v, "zmax": zmax, "status": code}
+
+
 def cpu_baseline(n=256, order=4):
     """The FP64 oracle, as it stands, on the host cores: one RK3 step of TGV n^3."""
     import oracle
@@ -137,6 +174,12 @@ def main():
             extra[key] = {k: r[k] for k in ("value", "ms_per_step", "achieved_gbs", "frac", "tuning")}
             log("extra %s: %.1f Mpt-steps/s, %.0f GB/s (%.1f%%)" % (key, r["value"], r["achieved_gbs"],
                                                                     100 * r["frac"]))
+
+    if not args.no_extra:
+        rb = measure_batch(sbli, torch, 100)
+        extra["batched_f32_order4_64boxes"] = rb
+        log("extra batched: graph %.1f vs sequential %.1f Mpt-steps/s (x%.2f)" % (
+            rb["graph_value"], rb["sequential_value"], rb["speedup"]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -134,7 +134,8 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
  * sbli_variant_info: info = {tile x, tile y, load-ahead depth} of a variant.
  * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
- *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).
+ *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).  sbli_set_tuning waits
+ *   for the context's stream (it updates a small device table).
  * sbli_autotune: time every variant with several zchunks (hipEvents on the
  *   context's stream, `reps` RK3 steps each after one warm-up step) using the
  *   caller's device buffers, then select the fastest; *best_ms (may be NULL)
@@ -146,6 +147,59 @@ int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]);
 int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk);
 int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk);
 int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms);
+
+/*
+ * Ensembles ("batches") of independent periodic boxes: cubic grids of uneven
+ * size with their own Re, Mach, Pr, gamma, time step and Taylor-Green phase,
+ * sharing one order and dtype.  Every RK3 stage of every box is one launch of
+ * the fused stage kernel, whose workgroups are split between the boxes by a
+ * device table; nsteps of such launches can be recorded once into a hipGraph
+ * and replayed with a single call.  Boxes are packed back to back in caller
+ * buffers: box i occupies elements [offsets[i], offsets[i+1]) with its own
+ * q[f][z][y][x] layout (sbli_batch_layout).  Every box is a 2*pi periodic cube.
+ * Results are bitwise identical to stepping each box with its own context
+ * (sbli_batch_step_sequential) in the same launch configuration.
+ *
+ * sbli_instance: n (>= 2*order+1) points per axis, Re, Mach, Pr > 0,
+ *   gamma > 1, dt > 0 its time step, phase the shift of its initial state.
+ * sbli_batch_init: validate and set up `count` boxes; *out receives the batch.
+ * sbli_batch_layout: offsets[0..count] (count+1 entries, elements).
+ * sbli_batch_tgv_init: Taylor-Green initial state of every box.
+ * sbli_batch_step: nsteps steps of every box, 3 launches per step.
+ * sbli_batch_step_sequential: the same, each box by its own sbli_rk3_step
+ *   (3 launches per box per step: the reference the ensemble is timed against).
+ * sbli_batch_capture: record nsteps steps on the given buffers into a hipGraph
+ *   (replacing any earlier one); the buffers must stay valid while it is used.
+ * sbli_batch_launch: replay the recorded graph on the batch's stream.
+ * sbli_batch_diagnostics: out[7*i .. 7*i+6] = sbli_diagnostics of box i;
+ *   returns SBLI_ERR_NONFINITE if any box is flagged.  Synchronises the stream.
+ * sbli_batch_set_tuning / get_tuning / autotune: variant (as for a single box)
+ *   and the cap on z-planes per workgroup (zmax); changing them drops the graph.
+ * In all calls q, q_tmp, dq are distinct device buffers of offsets[count]
+ * elements; the result is in q.
+ */
+typedef struct sbli_instance {
+    int n;
+    double Re, Mach, Pr, gamma;
+    double dt;
+    double phase[3];
+} sbli_instance;
+
+typedef struct sbli_batch sbli_batch;
+
+int sbli_batch_init(const sbli_instance* inst, int count, int order, int dtype, void* hip_stream, sbli_batch** out);
+int sbli_batch_destroy(sbli_batch* b);
+const char* sbli_batch_last_error(const sbli_batch* b);
+int sbli_batch_layout(const sbli_batch* b, size_t* offsets);
+int sbli_batch_tgv_init(sbli_batch* b, void* q);
+int sbli_batch_step(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps);
+int sbli_batch_step_sequential(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps);
+int sbli_batch_capture(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps);
+int sbli_batch_launch(sbli_batch* b);
+int sbli_batch_diagnostics(sbli_batch* b, const void* q, double* out);
+int sbli_batch_set_tuning(sbli_batch* b, int variant, int zmax);
+int sbli_batch_get_tuning(const sbli_batch* b, int* variant, int* zmax);
+int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq, int reps, double* best_ms);
 
 #ifdef __cplusplus
 }

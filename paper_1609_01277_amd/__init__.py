@@ -109,3 +109,102 @@ class Solver:
     def autotune(self, reps=2, force=False, path=None):
         kw = {} if path is None else {"path": path}
         return tuning.autotune(self, reps=reps, force=force, **kw)
+
+
+class Batch:
+    """An ensemble of periodic Taylor-Green boxes on the current HIP device and stream.
+
+    `instances` is a list of dicts with keys n, Re, Mach, Pr, gamma, dt, phase
+    (see synth.batch_instances).  States are flat torch tensors holding every box
+    back to back; `view(q, i)` gives box i as a (5, n, n, n) tensor.
+    """
+
+    def __init__(self, instances, order=4, dtype="f32", stream=None):
+        import torch
+        self.torch = torch
+        self.instances = [dict(d) for d in instances]
+        self.count = len(instances)
+        self.order = order
+        self.dtype = torch.float64 if dtype == "f64" else torch.float32
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        recs = [_lib.sbli_instance(int(d["n"]), float(d["Re"]), float(d["Mach"]), float(d["Pr"]),
+                                   float(d["gamma"]), float(d["dt"]),
+                                   (ctypes_double3(d.get("phase", (0.0, 0.0, 0.0)))))
+                for d in instances]
+        self.b = _lib.sbli_batch_init(recs, order, SBLI_F64 if dtype == "f64" else SBLI_F32,
+                                      stream.cuda_stream)
+        self.offsets = _lib.sbli_batch_layout(self.b, self.count)
+        self.total = self.offsets[-1]
+
+    def close(self):
+        if self.b:
+            _lib.sbli_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def points(self):
+        return sum(int(d["n"]) ** 3 for d in self.instances)
+
+    def empty_state(self):
+        return self.torch.empty(self.total, dtype=self.dtype, device="cuda")
+
+    def view(self, q, i):
+        n = int(self.instances[i]["n"])
+        return q[self.offsets[i]:self.offsets[i + 1]].view(5, n, n, n)
+
+    def _chk(self, *ts):
+        for t in ts:
+            if not (t.is_cuda and t.is_contiguous() and t.numel() == self.total and t.dtype == self.dtype):
+                raise ValueError("batch states must be contiguous CUDA tensors of %d elements, dtype %s"
+                                 % (self.total, self.dtype))
+
+    def tgv_init(self, q):
+        self._chk(q)
+        _lib.sbli_batch_tgv_init(self.b, q)
+        return q
+
+    def step(self, q, q_tmp, dq, nsteps=1):
+        self._chk(q, q_tmp, dq)
+        _lib.sbli_batch_step(self.b, q, q_tmp, dq, nsteps)
+        return q
+
+    def step_sequential(self, q, q_tmp, dq, nsteps=1):
+        self._chk(q, q_tmp, dq)
+        _lib.sbli_batch_step_sequential(self.b, q, q_tmp, dq, nsteps)
+        return q
+
+    def capture(self, q, q_tmp, dq, nsteps):
+        self._chk(q, q_tmp, dq)
+        _lib.sbli_batch_capture(self.b, q, q_tmp, dq, nsteps)
+
+    def launch(self):
+        _lib.sbli_batch_launch(self.b)
+
+    def diagnostics(self, q, check=True):
+        self._chk(q)
+        return _lib.sbli_batch_diagnostics(self.b, q, self.count, check=check)
+
+    def set_tuning(self, variant, zmax):
+        _lib.sbli_batch_set_tuning(self.b, variant, zmax)
+
+    def get_tuning(self):
+        return _lib.sbli_batch_get_tuning(self.b)
+
+    def autotune(self, reps=2):
+        q, qt, dq = self.empty_state(), self.empty_state(), self.empty_state()
+        self.tgv_init(q)
+        ms = _lib.sbli_batch_autotune(self.b, q, qt, dq, reps)
+        del q, qt, dq
+        return ms
+
+
+def ctypes_double3(v):
+    import ctypes
+    return (ctypes.c_double * 3)(*[float(x) for x in v])

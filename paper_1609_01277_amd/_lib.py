@@ -154,3 +154,111 @@ def sbli_autotune(ctx, q, q_tmp, dq, dt, reps=2):
     _check(load().sbli_autotune(ctx, _ptr(q), _ptr(q_tmp), _ptr(dq), float(dt), int(reps),
                                 ctypes.byref(ms)), ctx)
     return ms.value
+
+
+class sbli_instance(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("Re", ctypes.c_double), ("Mach", ctypes.c_double),
+                ("Pr", ctypes.c_double), ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("phase", ctypes.c_double * 3)]
+
+
+_batch_ready = False
+
+
+def _batch_lib():
+    global _batch_ready
+    lib = load()
+    if not _batch_ready:
+        vp = ctypes.c_void_p
+        ip = ctypes.POINTER(ctypes.c_int)
+        lib.sbli_batch_init.argtypes = [ctypes.POINTER(sbli_instance), ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, vp, ctypes.POINTER(vp)]
+        lib.sbli_batch_destroy.argtypes = [vp]
+        lib.sbli_batch_last_error.argtypes = [vp]
+        lib.sbli_batch_last_error.restype = ctypes.c_char_p
+        lib.sbli_batch_layout.argtypes = [vp, ctypes.POINTER(ctypes.c_size_t)]
+        lib.sbli_batch_tgv_init.argtypes = [vp, vp]
+        for name in ("sbli_batch_step", "sbli_batch_step_sequential", "sbli_batch_capture"):
+            getattr(lib, name).argtypes = [vp, vp, vp, vp, ctypes.c_int]
+        lib.sbli_batch_launch.argtypes = [vp]
+        lib.sbli_batch_diagnostics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
+        lib.sbli_batch_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+        lib.sbli_batch_get_tuning.argtypes = [vp, ip, ip]
+        lib.sbli_batch_autotune.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        for name in ("sbli_batch_init", "sbli_batch_destroy", "sbli_batch_layout", "sbli_batch_tgv_init",
+                     "sbli_batch_step", "sbli_batch_step_sequential", "sbli_batch_capture",
+                     "sbli_batch_launch", "sbli_batch_diagnostics", "sbli_batch_set_tuning",
+                     "sbli_batch_get_tuning", "sbli_batch_autotune"):
+            getattr(lib, name).restype = ctypes.c_int
+        _batch_ready = True
+    return lib
+
+
+def _bcheck(code, b):
+    if code not in (SBLI_OK,):
+        msg = _batch_lib().sbli_batch_last_error(b)
+        raise SbliError(code, msg.decode() if msg else "")
+    return code
+
+
+def sbli_batch_init(instances, order, dtype, stream=None):
+    arr = (sbli_instance * len(instances))(*instances)
+    out = ctypes.c_void_p()
+    _bcheck(_batch_lib().sbli_batch_init(arr, len(instances), int(order), int(dtype), stream,
+                                         ctypes.byref(out)), None)
+    return out.value
+
+
+def sbli_batch_destroy(b):
+    return _bcheck(_batch_lib().sbli_batch_destroy(b), None)
+
+
+def sbli_batch_layout(b, count):
+    off = (ctypes.c_size_t * (count + 1))()
+    _bcheck(_batch_lib().sbli_batch_layout(b, off), b)
+    return list(off)
+
+
+def sbli_batch_tgv_init(b, q):
+    return _bcheck(_batch_lib().sbli_batch_tgv_init(b, _ptr(q)), b)
+
+
+def sbli_batch_step(b, q, q_tmp, dq, nsteps):
+    return _bcheck(_batch_lib().sbli_batch_step(b, _ptr(q), _ptr(q_tmp), _ptr(dq), int(nsteps)), b)
+
+
+def sbli_batch_step_sequential(b, q, q_tmp, dq, nsteps):
+    return _bcheck(_batch_lib().sbli_batch_step_sequential(b, _ptr(q), _ptr(q_tmp), _ptr(dq), int(nsteps)), b)
+
+
+def sbli_batch_capture(b, q, q_tmp, dq, nsteps):
+    return _bcheck(_batch_lib().sbli_batch_capture(b, _ptr(q), _ptr(q_tmp), _ptr(dq), int(nsteps)), b)
+
+
+def sbli_batch_launch(b):
+    return _bcheck(_batch_lib().sbli_batch_launch(b), b)
+
+
+def sbli_batch_diagnostics(b, q, count, check=True):
+    out = (ctypes.c_double * (7 * count))()
+    code = _batch_lib().sbli_batch_diagnostics(b, _ptr(q), out)
+    if code not in (SBLI_OK, SBLI_ERR_NONFINITE) or (check and code != SBLI_OK):
+        _bcheck(code, b)
+    return [list(out[7 * i:7 * i + 7]) for i in range(count)], code
+
+
+def sbli_batch_set_tuning(b, variant, zmax):
+    return _bcheck(_batch_lib().sbli_batch_set_tuning(b, int(variant), int(zmax)), b)
+
+
+def sbli_batch_get_tuning(b):
+    v, z = ctypes.c_int(), ctypes.c_int()
+    _bcheck(_batch_lib().sbli_batch_get_tuning(b, ctypes.byref(v), ctypes.byref(z)), b)
+    return v.value, z.value
+
+
+def sbli_batch_autotune(b, q, q_tmp, dq, reps=2):
+    ms = ctypes.c_double()
+    _bcheck(_batch_lib().sbli_batch_autotune(b, _ptr(q), _ptr(q_tmp), _ptr(dq), int(reps),
+                                             ctypes.byref(ms)), b)
+    return ms.value

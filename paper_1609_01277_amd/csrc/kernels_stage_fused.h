@@ -410,26 +410,47 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     }
 }
 
-// Single-box launch over a 1D grid of tiles x z-chunks.  Workgroups are handed
-// to the 8 XCDs round-robin by id; the id is remapped so that each XCD (with
-// its own L2) walks a contiguous run of neighbouring tiles, whose halos then
-// hit in that L2.
+// One periodic box of a launch: its constants, where its state starts in the
+// packed buffers, its time step and its share of the launch grid.
+template <typename T>
+struct BoxInst {
+    BoxConst<T> c;
+    int64_t offset;    // element offset of the box's state in q, dq and out
+    T dt;              // time step (multiplied by the launch's dt_scale)
+    int tiles_x, tiles_y, zchunk;
+    int first_wg;      // first logical workgroup of this box
+    int num_wg;        // tiles_x * tiles_y * ceil(nz / zchunk)
+};
+
+// One launch covers `ninst` boxes (one for a single solver, many for an
+// ensemble): a 1D grid whose logical workgroup ids are split between the boxes
+// by first_wg.  Workgroups are handed to the 8 XCDs round-robin by id; the id is
+// remapped so that each XCD (with its own L2) walks a contiguous run of
+// neighbouring tiles, whose halos then hit in that L2.
 template <typename T, int R, int TX, int TY, int MODE, int PRE>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
-    fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out, BoxConst<T> c, int zchunk,
-                       T dt, T A, T B) {
-    const int tiles_x = (c.n[0] + TX - 1) / TX;
-    const int tiles_y = (c.n[1] + TY - 1) / TY;
+    fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
+                       const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
     const int total = gridDim.x;
     const int w = blockIdx.x;
     const int lam = (total % 8 == 0) ? (w % 8) * (total / 8) + w / 8 : w;
-    const int tile = lam % (tiles_x * tiles_y);
-    const int chunk = lam / (tiles_x * tiles_y);
-    const int tx = tile % tiles_x;
-    const int ty = tile / tiles_x;
-    const int z0 = chunk * zchunk;
-    const int zc = min(zchunk, c.n[2] - z0);
-    fused_stage_body<T, R, TX, TY, MODE, PRE>(q, dq, out, c, tx * TX, ty * TY, z0, zc, dt, A, B);
+    int lo = 0, hi = ninst - 1;     // last box with first_wg <= lam
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (inst[mid].first_wg <= lam) lo = mid;
+        else hi = mid - 1;
+    }
+    const BoxInst<T>& b = inst[lo];
+    const int local = lam - b.first_wg;
+    const int tile = local % (b.tiles_x * b.tiles_y);
+    const int chunk = local / (b.tiles_x * b.tiles_y);
+    const int tx = tile % b.tiles_x;
+    const int ty = tile / b.tiles_x;
+    const int z0 = chunk * b.zchunk;
+    const int zc = min(b.zchunk, b.c.n[2] - z0);
+    T* dqb = dq ? dq + b.offset : nullptr;
+    fused_stage_body<T, R, TX, TY, MODE, PRE>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
+                                              b.dt * dt_scale, A, B);
 }
 
 }  // namespace sbli

@@ -5,8 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/sbli.h"
 #include "kernels_pointwise.h"
@@ -26,6 +28,9 @@ struct sbli_ctx {
     BoxConst<float> c32;
     int zchunk;             // z-planes per workgroup of the fused stage kernel
     int variant;            // index into the compiled stage variants of (dtype, order)
+    BoxInst<double> inst64; // launch table entry (host copy) of the box
+    BoxInst<float> inst32;
+    void* inst_dev;         // the same entry on the device
     double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
     double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
     double* diag_out;       // 10 doubles
@@ -83,6 +88,38 @@ static int default_zchunk(const sbli_ctx* x) {
     return zc;
 }
 
+static int num_variants(const sbli_ctx* ctx) {
+    return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::count(ctx->r) : StageDispatch<float>::count(ctx->r);
+}
+
+static StageVariant variant_of(const sbli_ctx* ctx, int v) {
+    return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::get(ctx->r, v) : StageDispatch<float>::get(ctx->r, v);
+}
+
+// Rebuilds the box's launch-table entry for the current variant and zchunk and
+// copies it to the device, ordered on the context's stream, then waits for the
+// copy so the host copy may change again.  The step time is 1 in the table;
+// each launch passes the actual dt as its scale.
+static hipError_t update_table(sbli_ctx* x) {
+    const StageVariant v = variant_of(x, x->variant);
+    if (x->p.dtype == SBLI_F64) {
+        x->inst64.c = x->c64;
+        x->inst64.offset = 0;
+        x->inst64.dt = 1.0;
+        set_box_geometry(x->inst64, v.tx, v.ty, x->zchunk, 0);
+        hipError_t e = hipMemcpyAsync(x->inst_dev, &x->inst64, sizeof(x->inst64), hipMemcpyHostToDevice, x->stream);
+        return e == hipSuccess ? hipStreamSynchronize(x->stream) : e;
+    }
+    x->inst32.c = x->c32;
+    x->inst32.offset = 0;
+    x->inst32.dt = 1.0f;
+    set_box_geometry(x->inst32, v.tx, v.ty, x->zchunk, 0);
+    hipError_t e = hipMemcpyAsync(x->inst_dev, &x->inst32, sizeof(x->inst32), hipMemcpyHostToDevice, x->stream);
+    return e == hipSuccess ? hipStreamSynchronize(x->stream) : e;
+}
+
+static int total_wg(const sbli_ctx* x) { return x->p.dtype == SBLI_F64 ? x->inst64.num_wg : x->inst32.num_wg; }
+
 static size_t elem_size(const sbli_ctx* x) { return x->p.dtype == SBLI_F32 ? sizeof(float) : sizeof(double); }
 static int64_t npoints(const sbli_ctx* x) { return (int64_t)x->p.nx * x->p.ny * x->p.nz; }
 
@@ -131,6 +168,8 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_part, sizeof(double) * kDiagBlocks * (2 * kDiagQ + 3));
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_da, sizeof(double) * 3 * kMaxR);
     if (e == hipSuccess) e = hipMalloc((void**)&x->diag_out, sizeof(double) * 10);
+    if (e == hipSuccess) e = hipMalloc(&x->inst_dev, sizeof(BoxInst<double>));
+    if (e == hipSuccess) e = update_table(x);
     if (e == hipSuccess) {
         double da[3 * kMaxR];
         for (int d = 0; d < 3; ++d)
@@ -144,6 +183,7 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
         hipFree(x->diag_part);
         hipFree(x->diag_da);
         hipFree(x->diag_out);
+        hipFree(x->inst_dev);
         delete x;
         return code;
     }
@@ -157,6 +197,7 @@ extern "C" int sbli_destroy(sbli_ctx* ctx) {
     hipFree(ctx->diag_part);
     hipFree(ctx->diag_da);
     hipFree(ctx->diag_out);
+    hipFree(ctx->inst_dev);
     delete ctx;
     return SBLI_OK;
 }
@@ -183,16 +224,12 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
     return SBLI_OK;
 }
 
-static int num_variants(const sbli_ctx* ctx) {
-    return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::count(ctx->r) : StageDispatch<float>::count(ctx->r);
-}
-
 static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
-    const StageArgs a{ctx->stream, ctx->zchunk, mode, dt, A, B};
+    const StageArgs a{ctx->stream, ctx->inst_dev, 1, total_wg(ctx), mode, dt, A, B};
     if (ctx->p.dtype == SBLI_F64)
-        StageDispatch<double>::launch(ctx->r, ctx->variant, a, ctx->c64, (const double*)qin, (double*)dq, (double*)qout);
+        StageDispatch<double>::launch(ctx->r, ctx->variant, a, (const double*)qin, (double*)dq, (double*)qout);
     else
-        StageDispatch<float>::launch(ctx->r, ctx->variant, a, ctx->c32, (const float*)qin, (float*)dq, (float*)qout);
+        StageDispatch<float>::launch(ctx->r, ctx->variant, a, (const float*)qin, (float*)dq, (float*)qout);
 }
 
 extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
@@ -278,8 +315,7 @@ extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]) 
     if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
     if (variant < 0 || variant >= num_variants(ctx))
         return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
-    const StageVariant v = ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::get(ctx->r, variant)
-                                                    : StageDispatch<float>::get(ctx->r, variant);
+    const StageVariant v = variant_of(ctx, variant);
     info[0] = v.tx;
     info[1] = v.ty;
     info[2] = v.pre;
@@ -294,6 +330,7 @@ extern "C" int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk) {
         return fail(ctx, SBLI_ERR_ARG, "sbli_set_tuning: zchunk %d out of range [1, %d]", zchunk, ctx->p.nz);
     ctx->variant = variant;
     ctx->zchunk = zchunk;
+    HIP_TRY(ctx, update_table(ctx));
     return SBLI_OK;
 }
 
@@ -327,6 +364,7 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
         for (int ci = 0; ci < nc; ++ci) {
             ctx->variant = v;
             ctx->zchunk = cands[ci];
+            update_table(ctx);
             enqueue_steps(ctx, q, q_tmp, dq, dt, 1);          // warm-up
             hipEventRecord(e0, ctx->stream);
             enqueue_steps(ctx, q, q_tmp, dq, dt, reps);
@@ -337,6 +375,7 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
                 hipEventDestroy(e1);
                 ctx->variant = bv;
                 ctx->zchunk = bz;
+                update_table(ctx);
                 return fail(ctx, SBLI_ERR_HIP, "sbli_autotune: %s", hipGetErrorString(err));
             }
             float ms = 0.f;
@@ -352,6 +391,344 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
     hipEventDestroy(e1);
     ctx->variant = bv;
     ctx->zchunk = bz;
+    HIP_TRY(ctx, update_table(ctx));
+    if (best_ms) *best_ms = best / reps;
+    return SBLI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ensembles: many periodic boxes (uneven sizes and parameters) stepped by one
+// stage launch each, optionally recorded once into a hipGraph.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ void __launch_bounds__(256) copy_kernel(const T* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+struct sbli_batch {
+    int count = 0, order = 4, dtype = SBLI_F64, r = 2;
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;              // internal stream used only for graph capture
+    std::vector<sbli_ctx*> ctx;             // one context per box (constants, diagnostics scratch)
+    std::vector<sbli_instance> inst;
+    std::vector<size_t> off;                // element offsets, count + 1 entries
+    int variant = 0, zmax = 64;
+    std::vector<BoxInst<double>> t64;
+    std::vector<BoxInst<float>> t32;
+    void* table_dev = nullptr;
+    int total_wg = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+};
+
+static std::string g_batch_err;
+
+static int bfail(sbli_batch* b, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (b) b->err = buf;
+    else g_batch_err = buf;
+    return code;
+}
+
+#define BHIP_TRY(b, call)                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return bfail(b, SBLI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static size_t belem(const sbli_batch* b) { return b->dtype == SBLI_F32 ? sizeof(float) : sizeof(double); }
+
+static void batch_drop_graph(sbli_batch* b) {
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Rebuilds the launch table for the current variant and z-chunk cap, copies it
+// to the device (waiting for the copy) and gives every per-box context the same
+// launch configuration, so box-by-box stepping runs the same kernels.
+static int batch_build_table(sbli_batch* b) {
+    const StageVariant v = b->dtype == SBLI_F64 ? StageDispatch<double>::get(b->r, b->variant)
+                                                : StageDispatch<float>::get(b->r, b->variant);
+    int first = 0;
+    b->t64.assign(b->count, BoxInst<double>{});
+    b->t32.assign(b->count, BoxInst<float>{});
+    for (int i = 0; i < b->count; ++i) {
+        const int zc = std::min(b->inst[i].n, b->zmax);
+        if (b->dtype == SBLI_F64) {
+            BoxInst<double>& e = b->t64[i];
+            e.c = b->ctx[i]->c64;
+            e.offset = (int64_t)b->off[i];
+            e.dt = b->inst[i].dt;
+            first += set_box_geometry(e, v.tx, v.ty, zc, first);
+        } else {
+            BoxInst<float>& e = b->t32[i];
+            e.c = b->ctx[i]->c32;
+            e.offset = (int64_t)b->off[i];
+            e.dt = (float)b->inst[i].dt;
+            first += set_box_geometry(e, v.tx, v.ty, zc, first);
+        }
+        int rc = sbli_set_tuning(b->ctx[i], b->variant, zc);
+        if (rc != SBLI_OK) return bfail(b, rc, "batch: %s", sbli_last_error(b->ctx[i]));
+    }
+    b->total_wg = first;
+    const void* src = b->dtype == SBLI_F64 ? (const void*)b->t64.data() : (const void*)b->t32.data();
+    const size_t bytes = b->dtype == SBLI_F64 ? sizeof(BoxInst<double>) * b->count : sizeof(BoxInst<float>) * b->count;
+    BHIP_TRY(b, hipMemcpyAsync(b->table_dev, src, bytes, hipMemcpyHostToDevice, b->stream));
+    BHIP_TRY(b, hipStreamSynchronize(b->stream));
+    batch_drop_graph(b);
+    return SBLI_OK;
+}
+
+static void batch_launch_stage(sbli_batch* b, hipStream_t s, const void* qin, void* dq, void* qout, int k) {
+    const StageArgs a{s, b->table_dev, b->count, b->total_wg, kModeStage1 + k, 1.0, kRK_A[k], kRK_B[k]};
+    if (b->dtype == SBLI_F64)
+        StageDispatch<double>::launch(b->r, b->variant, a, (const double*)qin, (double*)dq, (double*)qout);
+    else
+        StageDispatch<float>::launch(b->r, b->variant, a, (const float*)qin, (float*)dq, (float*)qout);
+}
+
+// nsteps steps of every box, 3 launches per step; a final copy kernel puts the
+// result back in q when it ended in q_tmp.
+static void batch_enqueue(sbli_batch* b, hipStream_t s, void* q, void* q_tmp, void* dq, int nsteps) {
+    void* src = q;
+    void* dst = q_tmp;
+    for (int st = 0; st < nsteps; ++st)
+        for (int k = 0; k < 3; ++k) {
+            batch_launch_stage(b, s, src, dq, dst, k);
+            std::swap(src, dst);
+        }
+    if (src != q) {
+        const int64_t n = (int64_t)b->off[b->count];
+        const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
+        if (b->dtype == SBLI_F64) copy_kernel<double><<<blocks, 256, 0, s>>>((const double*)src, (double*)q, n);
+        else copy_kernel<float><<<blocks, 256, 0, s>>>((const float*)src, (float*)q, n);
+    }
+}
+
+static int batch_check_buffers(sbli_batch* b, const char* who, void* q, void* q_tmp, void* dq) {
+    if (!q || !q_tmp || !dq) return bfail(b, SBLI_ERR_ARG, "%s: NULL state pointer", who);
+    const size_t bytes = b->off[b->count] * belem(b);
+    if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
+        return bfail(b, SBLI_ERR_ARG, "%s: q, q_tmp and dq must not overlap", who);
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_destroy(sbli_batch* b) {
+    if (!b) return SBLI_OK;
+    if (b->stream || b->ctx.size()) hipStreamSynchronize(b->stream);
+    batch_drop_graph(b);
+    if (b->cap) hipStreamDestroy(b->cap);
+    hipFree(b->table_dev);
+    for (sbli_ctx* c : b->ctx) sbli_destroy(c);
+    delete b;
+    return SBLI_OK;
+}
+
+extern "C" const char* sbli_batch_last_error(const sbli_batch* b) { return b ? b->err.c_str() : g_batch_err.c_str(); }
+
+extern "C" int sbli_batch_init(const sbli_instance* inst, int count, int order, int dtype, void* hip_stream,
+                               sbli_batch** out) {
+    if (!out) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: out is NULL");
+    *out = nullptr;
+    if (!inst || count < 1) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: need count >= 1 instances");
+    for (int i = 0; i < count; ++i)
+        if (!(inst[i].dt > 0 && std::isfinite(inst[i].dt)))
+            return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: instance %d: dt must be finite and > 0", i);
+    sbli_batch* b = new (std::nothrow) sbli_batch();
+    if (!b) return bfail(nullptr, SBLI_ERR_ALLOC, "sbli_batch_init: out of host memory");
+    b->count = count;
+    b->order = order;
+    b->dtype = dtype;
+    b->r = order / 2;
+    b->stream = (hipStream_t)hip_stream;
+    b->inst.assign(inst, inst + count);
+    b->off.assign(count + 1, 0);
+    for (int i = 0; i < count; ++i) {
+        sbli_params p{inst[i].n, inst[i].n, inst[i].n, 2 * M_PI, 2 * M_PI, 2 * M_PI, inst[i].Re, inst[i].Mach,
+                      inst[i].Pr, inst[i].gamma, order, dtype};
+        sbli_ctx* c = nullptr;
+        int rc = sbli_init(&p, hip_stream, &c);
+        if (rc != SBLI_OK) {
+            bfail(nullptr, rc, "sbli_batch_init: instance %d: %s", i, sbli_last_error(nullptr));
+            sbli_batch_destroy(b);
+            return rc;
+        }
+        b->ctx.push_back(c);
+        b->off[i + 1] = b->off[i] + 5 * (size_t)inst[i].n * inst[i].n * inst[i].n;
+    }
+    hipError_t e = hipMalloc(&b->table_dev, sizeof(BoxInst<double>) * count);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        bfail(nullptr, SBLI_ERR_HIP, "sbli_batch_init: %s", hipGetErrorString(e));
+        sbli_batch_destroy(b);
+        return SBLI_ERR_HIP;
+    }
+    int rc = batch_build_table(b);
+    if (rc != SBLI_OK) {
+        g_batch_err = b->err;
+        sbli_batch_destroy(b);
+        return rc;
+    }
+    *out = b;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_layout(const sbli_batch* b, size_t* offsets) {
+    if (!b || !offsets) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_layout: NULL argument");
+    for (int i = 0; i <= b->count; ++i) offsets[i] = b->off[i];
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_tgv_init(sbli_batch* b, void* q) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_tgv_init: batch is NULL");
+    if (!q) return bfail(b, SBLI_ERR_ARG, "sbli_batch_tgv_init: q is NULL");
+    for (int i = 0; i < b->count; ++i) {
+        int rc = sbli_tgv_init(b->ctx[i], (char*)q + b->off[i] * belem(b), b->inst[i].phase);
+        if (rc != SBLI_OK) return bfail(b, rc, "sbli_batch_tgv_init: %s", sbli_last_error(b->ctx[i]));
+    }
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_step(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_step: batch is NULL");
+    int rc = batch_check_buffers(b, "sbli_batch_step", q, q_tmp, dq);
+    if (rc != SBLI_OK) return rc;
+    if (nsteps < 0) return bfail(b, SBLI_ERR_ARG, "sbli_batch_step: nsteps < 0");
+    batch_enqueue(b, b->stream, q, q_tmp, dq, nsteps);
+    BHIP_TRY(b, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_step_sequential(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_step_sequential: batch is NULL");
+    int rc = batch_check_buffers(b, "sbli_batch_step_sequential", q, q_tmp, dq);
+    if (rc != SBLI_OK) return rc;
+    if (nsteps < 0) return bfail(b, SBLI_ERR_ARG, "sbli_batch_step_sequential: nsteps < 0");
+    const size_t es = belem(b);
+    for (int i = 0; i < b->count; ++i) {
+        rc = sbli_rk3_step(b->ctx[i], (char*)q + b->off[i] * es, (char*)q_tmp + b->off[i] * es,
+                           (char*)dq + b->off[i] * es, b->inst[i].dt, nsteps);
+        if (rc != SBLI_OK) return bfail(b, rc, "sbli_batch_step_sequential: %s", sbli_last_error(b->ctx[i]));
+    }
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_capture(sbli_batch* b, void* q, void* q_tmp, void* dq, int nsteps) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_capture: batch is NULL");
+    int rc = batch_check_buffers(b, "sbli_batch_capture", q, q_tmp, dq);
+    if (rc != SBLI_OK) return rc;
+    if (nsteps < 1) return bfail(b, SBLI_ERR_ARG, "sbli_batch_capture: nsteps must be >= 1");
+    batch_drop_graph(b);
+    BHIP_TRY(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    batch_enqueue(b, b->cap, q, q_tmp, dq, nsteps);
+    hipError_t le = hipGetLastError();
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(b->cap, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return bfail(b, SBLI_ERR_HIP, "sbli_batch_capture: %s",
+                     hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    b->graph = g;
+    hipError_t ie = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+        batch_drop_graph(b);
+        return bfail(b, SBLI_ERR_HIP, "sbli_batch_capture: hipGraphInstantiate: %s", hipGetErrorString(ie));
+    }
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_launch(sbli_batch* b) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_launch: batch is NULL");
+    if (!b->exec) return bfail(b, SBLI_ERR_ARG, "sbli_batch_launch: nothing captured (call sbli_batch_capture)");
+    BHIP_TRY(b, hipGraphLaunch(b->exec, b->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_diagnostics(sbli_batch* b, const void* q, double* out) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_diagnostics: batch is NULL");
+    if (!q || !out) return bfail(b, SBLI_ERR_ARG, "sbli_batch_diagnostics: NULL pointer");
+    int status = SBLI_OK;
+    for (int i = 0; i < b->count; ++i) {
+        int rc = sbli_diagnostics(b->ctx[i], (const char*)q + b->off[i] * belem(b), out + 7 * i);
+        if (rc == SBLI_ERR_NONFINITE) {
+            status = rc;
+            bfail(b, rc, "sbli_batch_diagnostics: instance %d: %s", i, sbli_last_error(b->ctx[i]));
+        } else if (rc != SBLI_OK) {
+            return bfail(b, rc, "sbli_batch_diagnostics: instance %d: %s", i, sbli_last_error(b->ctx[i]));
+        }
+    }
+    return status;
+}
+
+extern "C" int sbli_batch_set_tuning(sbli_batch* b, int variant, int zmax) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_set_tuning: batch is NULL");
+    const int nv = b->dtype == SBLI_F64 ? StageDispatch<double>::count(b->r) : StageDispatch<float>::count(b->r);
+    if (variant < 0 || variant >= nv)
+        return bfail(b, SBLI_ERR_ARG, "sbli_batch_set_tuning: variant %d out of range [0, %d)", variant, nv);
+    if (zmax < 1) return bfail(b, SBLI_ERR_ARG, "sbli_batch_set_tuning: zmax must be >= 1");
+    b->variant = variant;
+    b->zmax = zmax;
+    return batch_build_table(b);
+}
+
+extern "C" int sbli_batch_get_tuning(const sbli_batch* b, int* variant, int* zmax) {
+    if (!b || !variant || !zmax) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_get_tuning: NULL argument");
+    *variant = b->variant;
+    *zmax = b->zmax;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq, int reps, double* best_ms) {
+    if (!b) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_autotune: batch is NULL");
+    int rc = batch_check_buffers(b, "sbli_batch_autotune", q, q_tmp, dq);
+    if (rc != SBLI_OK) return rc;
+    if (reps < 1) return bfail(b, SBLI_ERR_ARG, "sbli_batch_autotune: reps must be >= 1");
+    const int nv = b->dtype == SBLI_F64 ? StageDispatch<double>::count(b->r) : StageDispatch<float>::count(b->r);
+    const int zc[4] = {128, 64, 32, 16};
+    hipEvent_t e0, e1;
+    BHIP_TRY(b, hipEventCreate(&e0));
+    BHIP_TRY(b, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bv = b->variant, bz = b->zmax;
+    for (int v = 0; v < nv; ++v)
+        for (int zi = 0; zi < 4; ++zi) {
+            b->variant = v;
+            b->zmax = zc[zi];
+            rc = batch_build_table(b);
+            if (rc != SBLI_OK) break;
+            batch_enqueue(b, b->stream, q, q_tmp, dq, 1);
+            hipEventRecord(e0, b->stream);
+            batch_enqueue(b, b->stream, q, q_tmp, dq, reps);
+            hipEventRecord(e1, b->stream);
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                rc = SBLI_ERR_HIP;
+                break;
+            }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            if (ms < best) {
+                best = ms;
+                bv = v;
+                bz = zc[zi];
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    b->variant = bv;
+    b->zmax = bz;
+    int rc2 = batch_build_table(b);
+    if (rc != SBLI_OK) return bfail(b, rc, "sbli_batch_autotune: a timing run failed");
+    if (rc2 != SBLI_OK) return rc2;
     if (best_ms) *best_ms = best / reps;
     return SBLI_OK;
 }

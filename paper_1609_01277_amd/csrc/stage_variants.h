@@ -25,35 +25,37 @@ struct StageVariant {
 #define SBLI_VARIANTS_F3(X) X(16, 16, 0) X(16, 16, 1) X(16, 8, 1)
 #define SBLI_VARIANTS_F4(X) X(16, 8, 0) X(16, 8, 1) X(16, 4, 1)
 
+// One launch: the boxes (device table), their total workgroup count, the mode
+// and the RK coefficients.
 struct StageArgs {
     hipStream_t stream;
-    int zchunk;
+    const void* inst;   // device array of BoxInst<T>
+    int ninst;
+    int total_wg;
     int mode;
-    double dt, A, B;
+    double dt_scale, A, B;
 };
 
 template <typename T, int R, int TX, int TY, int PRE, int MODE>
-inline void launch_fused_cfg(const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
-    const int tiles = ((c.n[0] + TX - 1) / TX) * ((c.n[1] + TY - 1) / TY);
-    const int chunks = (c.n[2] + a.zchunk - 1) / a.zchunk;
-    fused_stage_kernel<T, R, TX, TY, MODE, PRE><<<dim3(tiles * chunks), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
-        qin, dq, qout, c, a.zchunk, (T)a.dt, (T)a.A, (T)a.B);
+inline void launch_fused_cfg(const StageArgs& a, const T* qin, T* dq, T* qout) {
+    fused_stage_kernel<T, R, TX, TY, MODE, PRE><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
+        qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
 }
 
 template <typename T, int R, int TX, int TY, int PRE>
-inline bool try_variant(int& k, int want, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
+inline bool try_variant(int& k, int want, const StageArgs& a, const T* qin, T* dq, T* qout) {
     if (k++ != want) return false;
     switch (a.mode) {
-        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, kModeRHS>(a, c, qin, dq, qout); break;
-        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage1>(a, c, qin, dq, qout); break;
-        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage2>(a, c, qin, dq, qout); break;
-        default: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage3>(a, c, qin, dq, qout); break;
+        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, kModeRHS>(a, qin, dq, qout); break;
+        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage1>(a, qin, dq, qout); break;
+        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage2>(a, qin, dq, qout); break;
+        default: launch_fused_cfg<T, R, TX, TY, PRE, kModeStage3>(a, qin, dq, qout); break;
     }
     return true;
 }
 
 #define SBLI_TRY(TX_, TY_, PRE_) \
-    if (try_variant<T, R, TX_, TY_, PRE_>(k, v, a, c, qin, dq, qout)) return true;
+    if (try_variant<T, R, TX_, TY_, PRE_>(k, v, a, qin, dq, qout)) return true;
 #define SBLI_ENTRY(TX_, TY_, PRE_) StageVariant{TX_, TY_, PRE_},
 
 template <typename T, int R>
@@ -72,7 +74,7 @@ struct VariantSet;
             static const StageVariant t[] = {LIST(SBLI_ENTRY)};                                          \
             return t[i];                                                                                  \
         }                                                                                                 \
-        static bool launch(int v, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) { \
+        static bool launch(int v, const StageArgs& a, const T* qin, T* dq, T* qout) {                   \
             int k = 0;                                                                                    \
             LIST(SBLI_TRY)                                                                                \
             return false;                                                                                 \
@@ -111,14 +113,26 @@ struct StageDispatch {
             default: return VariantSet<T, 4>::get(i);
         }
     }
-    static bool launch(int r, int v, const StageArgs& a, const BoxConst<T>& c, const T* qin, T* dq, T* qout) {
+    static bool launch(int r, int v, const StageArgs& a, const T* qin, T* dq, T* qout) {
         switch (r) {
-            case 1: return VariantSet<T, 1>::launch(v, a, c, qin, dq, qout);
-            case 2: return VariantSet<T, 2>::launch(v, a, c, qin, dq, qout);
-            case 3: return VariantSet<T, 3>::launch(v, a, c, qin, dq, qout);
-            default: return VariantSet<T, 4>::launch(v, a, c, qin, dq, qout);
+            case 1: return VariantSet<T, 1>::launch(v, a, qin, dq, qout);
+            case 2: return VariantSet<T, 2>::launch(v, a, qin, dq, qout);
+            case 3: return VariantSet<T, 3>::launch(v, a, qin, dq, qout);
+            default: return VariantSet<T, 4>::launch(v, a, qin, dq, qout);
         }
     }
 };
+
+// Fills the launch-geometry part of a box entry for tile (tx, ty) and zchunk;
+// returns the number of workgroups the box takes.
+template <typename T>
+inline int set_box_geometry(BoxInst<T>& b, int tx, int ty, int zchunk, int first_wg) {
+    b.tiles_x = (b.c.n[0] + tx - 1) / tx;
+    b.tiles_y = (b.c.n[1] + ty - 1) / ty;
+    b.zchunk = zchunk;
+    b.first_wg = first_wg;
+    b.num_wg = b.tiles_x * b.tiles_y * ((b.c.n[2] + zchunk - 1) / zchunk);
+    return b.num_wg;
+}
 
 }  // namespace sbli

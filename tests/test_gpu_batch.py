@@ -1,0 +1,122 @@
+"""Ensembles of uneven Taylor-Green boxes: one launch per stage over all boxes, and the
+same launches recorded in a hipGraph, against box-by-box stepping and the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _sbli():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a HIP device")
+    import paper_1609_01277_amd as sbli
+    return sbli, torch
+
+
+def small_ensemble(count=5, seed=7):
+    return synth.batch_instances(count=count, seed=seed, sizes=(32, 24, 40, 20, 33))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batched_equals_sequential_bitwise(dtype):
+    sbli, torch = _sbli()
+    insts = small_ensemble()
+    b = sbli.Batch(insts, order=4, dtype=dtype)
+    q1 = b.tgv_init(b.empty_state())
+    q2 = q1.clone()
+    b.step(q1, b.empty_state(), b.empty_state(), 3)
+    b.step_sequential(q2, b.empty_state(), b.empty_state(), 3)
+    assert torch.equal(q1, q2)
+    # and every box really moved
+    q0 = b.tgv_init(b.empty_state())
+    for i in range(b.count):
+        assert not torch.equal(b.view(q1, i), b.view(q0, i))
+
+
+@pytest.mark.parametrize("nsteps", [2, 3])
+def test_graph_replays_match_eager(nsteps):
+    sbli, torch = _sbli()
+    insts = small_ensemble(count=4, seed=11)
+    b = sbli.Batch(insts, order=4, dtype="f32")
+    q = b.tgv_init(b.empty_state())
+    qt, dq = b.empty_state(), b.empty_state()
+    ref = q.clone()
+    rt, rd = b.empty_state(), b.empty_state()
+    b.capture(q, qt, dq, nsteps)
+    for rep in range(3):
+        b.launch()
+        torch.cuda.synchronize()
+        b.step(ref, rt, rd, nsteps)            # eager work between replays
+        junk = torch.ones(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(q, ref), rep
+        assert float(junk) == 1000.0
+
+
+def test_batched_fp64_matches_oracle_per_box(oracle_mod):
+    sbli, torch = _sbli()
+    insts = small_ensemble(count=4, seed=3)
+    b = sbli.Batch(insts, order=4, dtype="f64")
+    q = b.empty_state()
+    refs = []
+    for i, d in enumerate(insts):
+        p = oracle.Params(n=(d["n"],) * 3, order=4, Re=d["Re"], Mach=d["Mach"], Pr=d["Pr"], gamma=d["gamma"])
+        q0 = oracle.tgv_init(p, phase=d["phase"])
+        b.view(q, i).copy_(torch.from_numpy(q0))
+        refs.append((p, oracle.rk3(q0, p, d["dt"], 2)))
+    b.step(q, b.empty_state(), b.empty_state(), 2)
+    diags, code = b.diagnostics(q)
+    assert code == sbli.SBLI_OK
+    for i, (p, ref) in enumerate(refs):
+        got = b.view(q, i).cpu().numpy()
+        mom = np.abs(ref[1:4]).max()
+        for f in range(5):
+            scale = mom if f in (1, 2, 3) else np.abs(ref[f]).max()
+            assert np.abs(got[f] - ref[f]).max() / scale <= 1e-12, (i, f)
+        dref, _ = oracle.diagnostics(ref, p)
+        for k in range(7):
+            assert abs(diags[i][k] - dref[k]) <= 1e-12 * max(1.0, abs(dref[k])), (i, k)
+
+
+def test_batched_tgv_init_phase_matches_oracle(oracle_mod):
+    sbli, torch = _sbli()
+    insts = small_ensemble(count=3, seed=5)
+    b = sbli.Batch(insts, order=4, dtype="f64")
+    q = b.tgv_init(b.empty_state())
+    for i, d in enumerate(insts):
+        p = oracle.Params(n=(d["n"],) * 3, order=4, Re=d["Re"], Mach=d["Mach"], Pr=d["Pr"], gamma=d["gamma"])
+        ref = oracle.tgv_init(p, phase=d["phase"])
+        assert np.abs(b.view(q, i).cpu().numpy() - ref).max() < 1e-13 * np.abs(ref).max()
+
+
+def test_full_ensemble_64_graph_equals_sequential():
+    """The 64-box ensemble (seed 1609, N in {32,48,64,96,128}, FP32): two steps through a
+    captured graph equal two box-by-box steps bitwise."""
+    sbli, torch = _sbli()
+    insts = synth.batch_instances()
+    b = sbli.Batch(insts, order=4, dtype="f32")
+    q = b.tgv_init(b.empty_state())
+    ref = q.clone()
+    b.capture(q, b.empty_state(), b.empty_state(), 2)
+    b.launch()
+    b.step_sequential(ref, b.empty_state(), b.empty_state(), 2)
+    torch.cuda.synchronize()
+    assert torch.equal(q, ref)
+    diags, code = b.diagnostics(q)
+    assert code == sbli.SBLI_OK and len(diags) == 64
+
+
+def test_batch_rejects_bad_instances():
+    sbli, torch = _sbli()
+    bad = small_ensemble(count=2)
+    bad[1]["n"] = 8
+    with pytest.raises(sbli.SbliError):
+        sbli.Batch(bad, order=4)
+    bad = small_ensemble(count=2)
+    bad[0]["dt"] = -1.0
+    with pytest.raises(sbli.SbliError):
+        sbli.Batch(bad, order=4)
