@@ -1,0 +1,201 @@
+"""Learned-closure study: data from filtered fine solutions, training, a-posteriori test.
+
+1. Fine Taylor-Green runs (256^3, FP64, order 4, dt 8.4625e-4) at Re in {800, 1600,
+   3200} to t = 10.  At evenly spaced times the state q_f is box-filtered to 64^3
+   (width 4 fine cells), together with its residual: the training pair is
+   (F q_f, C* = F R_f(q_f) - R_c(F q_f)), R_c the coarse 64^3 FP32 residual.
+2. Per-field standardisation from the pairs, Adam training of the closure network
+   (BF16 MFMA kernels of the library) on the pairs.
+3. A-posteriori: coarse 64^3 FP32 runs (dt 3.385e-3) from F q_f(0) to t = 10 with
+   and without the closure; filtered kinetic energy and enstrophy against those of
+   F q_f(t) (the filtered fine solution judges the error).
+
+Every arithmetic step runs in libsbli's kernels; torch only holds device memory and
+copies samples into batch buffers.  Writes one JSON file.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main(argv=None):
+    import torch
+
+    import synth
+    from paper_1609_01277_amd import Solver
+    from paper_1609_01277_amd import closure as cl
+
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--out", default="closure_study.json")
+    ap.add_argument("--nf", type=int, default=256)
+    ap.add_argument("--ratio", type=int, default=4)
+    ap.add_argument("--t-end", type=float, default=10.0)
+    ap.add_argument("--res", default="800,1600,3200")
+    ap.add_argument("--snapshots", type=int, default=2000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--seed", type=int, default=1609)
+    ap.add_argument("--guard", type=float, default=20.0, help="limit = |mean| + guard * std per field")
+    ap.add_argument("--diag-every", type=int, default=10, help="coarse steps between diagnostics")
+    args = ap.parse_args(argv)
+
+    torch.cuda.set_device(0)
+    nf, r = args.nf, args.ratio
+    nc = nf // r
+    Pc = nc ** 3
+    dt_f = synth.DT64 * 64.0 / nf
+    dt_c = dt_f * r
+    res = [float(v) for v in args.res.split(",")]
+    steps_f = int(round(args.t_end / dt_f))
+    per_re = [args.snapshots // len(res) + (1 if i < args.snapshots % len(res) else 0) for i in range(len(res))]
+    X = torch.empty((args.snapshots, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
+    Y = torch.empty_like(X)
+    out = {"config": vars(args), "nf": nf, "nc": nc, "dt_fine": dt_f, "dt_coarse": dt_c, "fine_steps": steps_f}
+    ref_diag = {}
+    k = 0
+    t0 = time.time()
+    for ri, Re in enumerate(res):
+        fine = Solver(nf, order=4, dtype="f64", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+        fine.autotune()
+        coarse = Solver(nc, order=4, dtype="f32", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+        q, qt, dq = fine.empty_state(), fine.empty_state(), fine.empty_state()
+        fine.tgv_init(q)
+        Rf = fine.empty_state()
+        fq = torch.empty((5, nc, nc, nc), dtype=torch.float32, device="cuda")
+        snap_steps = sorted(set(int(round(i * steps_f / max(per_re[ri] - 1, 1))) for i in range(per_re[ri])))
+        snap_set = set(snap_steps)
+        diag_every_f = args.diag_every * r
+        ek, en, times = [], [], []
+        for step in range(steps_f + 1):
+            if step in snap_set and k < args.snapshots:
+                cl.sbli_box_filter(q, nf, 5, r, X[k])
+                fine.rhs(q, Rf)
+                coarse.rhs(X[k], Y[k])                         # R_c(F q_f)
+                cl.sbli_box_filter(Rf, nf, 5, r, Y[k], subtract=True)   # C* = F R_f - R_c(F q_f)
+                k += 1
+            if step % diag_every_f == 0:
+                cl.sbli_box_filter(q, nf, 5, r, fq)
+                d, _ = coarse.diagnostics(fq, check=False)
+                ek.append(d["Ek"])
+                en.append(d["enstrophy"])
+                times.append(step * dt_f)
+            if step < steps_f:
+                fine.rk3_step(q, qt, dq, dt_f, 1)
+            if step % 2000 == 0:
+                log("Re %g: fine step %d / %d, %d snapshots, %.1f s" % (Re, step, steps_f, k, time.time() - t0))
+        ref_diag[Re] = {"t": times, "Ek": ek, "enstrophy": en}
+        del q, qt, dq, Rf
+        fine.close()
+        coarse.close()
+        torch.cuda.empty_cache()
+    out["data_seconds"] = time.time() - t0
+    nsnap = k
+    out["snapshots"] = nsnap
+
+    # ---- standardisation and training ----
+    net = cl.ClosureNet(nc, args.batch)
+    net.channel_stats(X[:nsnap], 0)
+    net.channel_stats(Y[:nsnap], 1)
+    st = net.get_stats()
+    st[20:25] = np.abs(st[10:15]) + args.guard * st[15:20]
+    net.set_stats(st)
+    out["stats"] = [float(v) for v in st]
+    net.set_params(synth.closure_init_params(args.seed))
+    rng = np.random.default_rng(args.seed)
+    xb = torch.empty((args.batch, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
+    yb = torch.empty_like(xb)
+    losses = []
+    steps_per_epoch = nsnap // args.batch
+    flop_per_sample = 2 * Pc * 27 * (8 * 32 + 32 * 32 + 32 * 32) * 3   # fwd + bwd-data + bwd-weight, padded
+    t1 = time.time()
+    torch.cuda.synchronize()
+    for ep in range(args.epochs):
+        perm = rng.permutation(nsnap)
+        tot = 0.0
+        for s in range(steps_per_epoch):
+            idx = perm[s * args.batch:(s + 1) * args.batch]
+            for j, i in enumerate(idx):
+                xb[j].copy_(X[int(i)])
+                yb[j].copy_(Y[int(i)])
+            tot += net.train_step(xb, yb, args.lr)
+        losses.append(tot / steps_per_epoch)
+        log("epoch %d: mean loss %.5f (%.1f s)" % (ep, losses[-1], time.time() - t1))
+    torch.cuda.synchronize()
+    train_s = time.time() - t1
+    nsteps_train = args.epochs * steps_per_epoch
+    out["training"] = {"epoch_loss": losses, "seconds": train_s, "steps": nsteps_train,
+                       "ms_per_step": 1e3 * train_s / max(nsteps_train, 1),
+                       "padded_tflops_per_s": flop_per_sample * args.batch * nsteps_train / train_s / 1e12,
+                       "note": "wall time per step includes host-side batch assembly and the loss read-back"}
+    # time the network kernels alone on one batch (no host work in the loop)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        net.gradients(xb, yb)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["training"]["fwd_bwd_ms_per_batch"] = ms
+    out["training"]["fwd_bwd_padded_tflops_per_s"] = flop_per_sample * args.batch / (ms * 1e-3) / 1e12
+
+    # ---- a-posteriori: coarse runs with and without the closure ----
+    steps_c = int(round(args.t_end / dt_c))
+    post = {}
+    for Re in res:
+        res_run = {}
+        for mode in ("plain", "closure"):
+            s = Solver(nc, order=4, dtype="f32", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+            fine = Solver(nf, order=4, dtype="f64", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+            qf = fine.tgv_init(fine.empty_state())
+            q = s.empty_state()
+            cl.sbli_box_filter(qf, nf, 5, r, q)
+            del qf
+            fine.close()
+            if mode == "closure":
+                cl.attach(s, net)
+            qt, dq = s.empty_state(), s.empty_state()
+            ek, en = [], []
+            t2 = time.time()
+            for step in range(steps_c + 1):
+                if step % args.diag_every == 0:
+                    d, code = s.diagnostics(q, check=False)
+                    ek.append(d["Ek"])
+                    en.append(d["enstrophy"])
+                if step < steps_c:
+                    s.rk3_step(q, qt, dq, dt_c, 1)
+            torch.cuda.synchronize()
+            refd = ref_diag[Re]
+            m = min(len(ek), len(refd["Ek"]))
+            e_ek = np.abs(np.array(ek[:m]) - np.array(refd["Ek"][:m])) / np.max(np.abs(refd["Ek"][:m]))
+            e_en = np.abs(np.array(en[:m]) - np.array(refd["enstrophy"][:m])) / np.max(np.abs(refd["enstrophy"][:m]))
+            entry = {"Ek_err_max": float(e_ek.max()), "Ek_err_rms": float(math.sqrt(np.mean(e_ek ** 2))),
+                     "enstrophy_err_max": float(e_en.max()), "enstrophy_err_rms": float(math.sqrt(np.mean(e_en ** 2))),
+                     "seconds": time.time() - t2, "Ek": ek, "enstrophy": en}
+            if mode == "closure":
+                entry["guard_accepted_rejected"] = list(cl.counts(s))
+                cl.attach(s, None)
+            res_run[mode] = entry
+            log("Re %g %s: Ek err max %.4f rms %.4f; enstrophy err max %.4f rms %.4f" % (
+                Re, mode, entry["Ek_err_max"], entry["Ek_err_rms"], entry["enstrophy_err_max"],
+                entry["enstrophy_err_rms"]))
+            s.close()
+        res_run["reference"] = ref_diag[Re]
+        post[str(Re)] = res_run
+    out["a_posteriori"] = post
+    with open(args.out, "w") as f:
+        json.dump(out, f)
+    log("wrote", args.out)
+
+
+if __name__ == "__main__":
+    main()

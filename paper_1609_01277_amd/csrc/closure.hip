@@ -1,0 +1,359 @@
+// libsbli: host side of the learned closure (include/sbli_closure.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <new>
+#include <string>
+
+#include "../../include/sbli.h"
+#include "../../include/sbli_closure.h"
+#include "closure_kernels.h"
+
+using namespace sbli;
+
+namespace {
+
+constexpr int kCh[4] = {5, 32, 32, 5};      // channels of the network
+constexpr int kCpad[4] = {8, 32, 32, 8};    // padded channel strides of the activations
+
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+struct Layer {
+    int cin, cout, cpad, opad;   // real and padded input / output channels
+    int Kf, Kb, Kpad32;          // packed forward / backward-data widths, weight-gradient width
+    size_t w_off, b_off;         // offsets of W [cout][cin][27] and b [cout] in the flat vector
+    __bf16* Wf = nullptr;        // [32][Kf]
+    __bf16* Wb = nullptr;        // [32][Kb]
+};
+
+}  // namespace
+
+struct sbli_net {
+    int n = 0, max_batch = 0;
+    int64_t P = 0;
+    hipStream_t stream = nullptr;
+    Layer L[kNetLayers];
+    int nparams = 0;
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    int adam_t = 0;
+    float* stats = nullptr;          // [0..9] input mean/std, [10..19] output mean/std, [20..24] guard limits
+    __bf16 *x = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *d2 = nullptr, *d1 = nullptr;
+    float *pre1 = nullptr, *pre2 = nullptr, *y = nullptr;
+    float* wpart = nullptr;          // weight-gradient partials
+    int wgrad_wg = 512;
+    double* loss_part = nullptr;
+    double* loss = nullptr;
+    std::string err;
+};
+
+static std::string g_net_err;
+
+static int nfail(sbli_net* net, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (net) net->err = buf;
+    else g_net_err = buf;
+    return code;
+}
+
+#define NHIP_TRY(net, call)                                                                          \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return nfail(net, SBLI_ERR_HIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+static unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+extern "C" const char* sbli_net_last_error(const sbli_net* net) { return net ? net->err.c_str() : g_net_err.c_str(); }
+
+extern "C" int sbli_net_destroy(sbli_net* net) {
+    if (!net) return SBLI_OK;
+    hipStreamSynchronize(net->stream);
+    for (int l = 0; l < kNetLayers; ++l) {
+        hipFree(net->L[l].Wf);
+        hipFree(net->L[l].Wb);
+    }
+    void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->stats, net->x, net->h1, net->h2,
+                    net->dy, net->d2, net->d1, net->pre1, net->pre2, net->y, net->wpart, net->loss_part, net->loss};
+    for (void* p : ptrs) hipFree(p);
+    delete net;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net** out) {
+    if (!out) return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_create: out is NULL");
+    *out = nullptr;
+    if (n < 32 || n % 32 != 0 || n > 1024)
+        return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_create: n must be a multiple of 32 in [32, 1024] (got %d)", n);
+    if (max_batch < 1 || (int64_t)max_batch * n * n * n > (int64_t)1 << 31)
+        return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_create: max_batch out of range");
+    sbli_net* net = new (std::nothrow) sbli_net();
+    if (!net) return nfail(nullptr, SBLI_ERR_ALLOC, "sbli_net_create: out of host memory");
+    net->n = n;
+    net->max_batch = max_batch;
+    net->P = (int64_t)n * n * n;
+    net->stream = (hipStream_t)hip_stream;
+    size_t off = 0;
+    for (int l = 0; l < kNetLayers; ++l) {
+        Layer& L = net->L[l];
+        L.cin = kCh[l];
+        L.cout = kCh[l + 1];
+        L.cpad = kCpad[l];
+        L.opad = kCpad[l + 1];
+        L.Kf = round_up(27 * L.cpad, 16);
+        L.Kb = round_up(27 * L.opad, 16);
+        L.Kpad32 = round_up(27 * L.cpad, 32);
+        L.w_off = off;
+        off += (size_t)L.cout * L.cin * 27;
+        L.b_off = off;
+        off += L.cout;
+    }
+    net->nparams = (int)off;
+    const int64_t NP = (int64_t)max_batch * net->P;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes);
+        if (e == hipSuccess) e = hipMemsetAsync(*p, 0, bytes, net->stream);
+    };
+    for (int l = 0; l < kNetLayers; ++l) {
+        alloc((void**)&net->L[l].Wf, sizeof(__bf16) * 32 * net->L[l].Kf);
+        alloc((void**)&net->L[l].Wb, sizeof(__bf16) * 32 * net->L[l].Kb);
+    }
+    alloc((void**)&net->params, sizeof(float) * net->nparams);
+    alloc((void**)&net->grads, sizeof(float) * net->nparams);
+    alloc((void**)&net->adam_m, sizeof(float) * net->nparams);
+    alloc((void**)&net->adam_v, sizeof(float) * net->nparams);
+    alloc((void**)&net->stats, sizeof(float) * 32);
+    alloc((void**)&net->x, sizeof(__bf16) * NP * 8);
+    alloc((void**)&net->h1, sizeof(__bf16) * NP * 32);
+    alloc((void**)&net->h2, sizeof(__bf16) * NP * 32);
+    alloc((void**)&net->dy, sizeof(__bf16) * NP * 8);
+    alloc((void**)&net->d2, sizeof(__bf16) * NP * 32);
+    alloc((void**)&net->d1, sizeof(__bf16) * NP * 32);
+    alloc((void**)&net->pre1, sizeof(float) * NP * 32);
+    alloc((void**)&net->pre2, sizeof(float) * NP * 32);
+    alloc((void**)&net->y, sizeof(float) * NP * 8);
+    alloc((void**)&net->wpart, sizeof(float) * (size_t)net->wgrad_wg * 32 * 27 * 32);
+    alloc((void**)&net->loss_part, sizeof(double) * nblk(NP));
+    alloc((void**)&net->loss, sizeof(double));
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) {
+        nfail(nullptr, e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP, "sbli_net_create: %s",
+              hipGetErrorString(e));
+        sbli_net_destroy(net);
+        return e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP;
+    }
+    // identity standardisation until set: mean 0, std 1, no guard limit
+    float st[32] = {0};
+    for (int c = 0; c < 5; ++c) {
+        st[5 + c] = 1.0f;
+        st[15 + c] = 1.0f;
+        st[20 + c] = INFINITY;
+    }
+    e = hipMemcpyAsync(net->stats, st, sizeof(st), hipMemcpyHostToDevice, net->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
+    if (e != hipSuccess) {
+        nfail(nullptr, SBLI_ERR_HIP, "sbli_net_create: %s", hipGetErrorString(e));
+        sbli_net_destroy(net);
+        return SBLI_ERR_HIP;
+    }
+    *out = net;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_num_params(const sbli_net* net) {
+    if (!net) return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_num_params: net is NULL");
+    return net->nparams;
+}
+
+static int pack_all(sbli_net* net) {
+    for (int l = 0; l < kNetLayers; ++l) {
+        const Layer& L = net->L[l];
+        const int tot = 32 * (L.Kf > L.Kb ? L.Kf : L.Kb);
+        pack_weights_kernel<<<nblk(tot), 256, 0, net->stream>>>(net->params + L.w_off, L.cin, L.cout, L.cpad, L.opad,
+                                                                L.Kf, L.Kb, L.Wf, L.Wb);
+    }
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_set_params(sbli_net* net, const float* host_params) {
+    if (!net || !host_params) return nfail(net, SBLI_ERR_ARG, "sbli_net_set_params: NULL argument");
+    NHIP_TRY(net, hipMemcpyAsync(net->params, host_params, sizeof(float) * net->nparams, hipMemcpyHostToDevice,
+                                 net->stream));
+    NHIP_TRY(net, hipMemsetAsync(net->adam_m, 0, sizeof(float) * net->nparams, net->stream));
+    NHIP_TRY(net, hipMemsetAsync(net->adam_v, 0, sizeof(float) * net->nparams, net->stream));
+    net->adam_t = 0;
+    int rc = pack_all(net);
+    if (rc != SBLI_OK) return rc;
+    NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_get_params(sbli_net* net, float* host_params) {
+    if (!net || !host_params) return nfail(net, SBLI_ERR_ARG, "sbli_net_get_params: NULL argument");
+    NHIP_TRY(net, hipMemcpyAsync(host_params, net->params, sizeof(float) * net->nparams, hipMemcpyDeviceToHost,
+                                 net->stream));
+    NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_get_grads(sbli_net* net, float* host_grads) {
+    if (!net || !host_grads) return nfail(net, SBLI_ERR_ARG, "sbli_net_get_grads: NULL argument");
+    NHIP_TRY(net, hipMemcpyAsync(host_grads, net->grads, sizeof(float) * net->nparams, hipMemcpyDeviceToHost,
+                                 net->stream));
+    NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_channel_stats(sbli_net* net, const float* data, int count, int which) {
+    if (!net || !data) return nfail(net, SBLI_ERR_ARG, "sbli_net_channel_stats: NULL argument");
+    if (count < 1 || (which != 0 && which != 1))
+        return nfail(net, SBLI_ERR_ARG, "sbli_net_channel_stats: count >= 1 and which in {0, 1} required");
+    channel_stats_kernel<<<5, 256, 0, net->stream>>>(data, count, net->P, net->stats + 10 * which);
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_set_stats(sbli_net* net, const float* host_stats) {
+    if (!net || !host_stats) return nfail(net, SBLI_ERR_ARG, "sbli_net_set_stats: NULL argument");
+    for (int c = 0; c < 5; ++c)
+        if (!(host_stats[5 + c] > 0) || !(host_stats[15 + c] > 0))
+            return nfail(net, SBLI_ERR_ARG, "sbli_net_set_stats: standard deviations must be > 0");
+    NHIP_TRY(net, hipMemcpyAsync(net->stats, host_stats, sizeof(float) * 25, hipMemcpyHostToDevice, net->stream));
+    NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_get_stats(sbli_net* net, float* host_stats) {
+    if (!net || !host_stats) return nfail(net, SBLI_ERR_ARG, "sbli_net_get_stats: NULL argument");
+    NHIP_TRY(net, hipMemcpyAsync(host_stats, net->stats, sizeof(float) * 25, hipMemcpyDeviceToHost, net->stream));
+    NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    return SBLI_OK;
+}
+
+// Forward pass of `batch` samples: x -> h1 -> h2 -> y (all in the net's buffers).
+static int forward_core(sbli_net* net, const float* q, int batch) {
+    const int64_t NP = (int64_t)batch * net->P;
+    standardize_kernel<<<nblk(NP), 256, 0, net->stream>>>(q, net->P, batch, net->stats, net->x);
+    const unsigned g = nblk(NP);
+    const Layer* L = net->L;
+    conv_mfma_kernel<kEpiGelu><<<g, 256, 0, net->stream>>>(net->x, L[0].cpad, L[0].Wf, L[0].Kf,
+                                                           net->params + L[0].b_off, net->n, NP, net->pre1, net->h1,
+                                                           nullptr, 32, 32);
+    conv_mfma_kernel<kEpiGelu><<<g, 256, 0, net->stream>>>(net->h1, L[1].cpad, L[1].Wf, L[1].Kf,
+                                                           net->params + L[1].b_off, net->n, NP, net->pre2, net->h2,
+                                                           nullptr, 32, 32);
+    conv_mfma_kernel<kEpiLinear><<<g, 256, 0, net->stream>>>(net->h2, L[2].cpad, L[2].Wf, L[2].Kf,
+                                                             net->params + L[2].b_off, net->n, NP, net->y, nullptr,
+                                                             nullptr, L[2].cout, 8);
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_forward(sbli_net* net, const float* q, int batch, float* out) {
+    if (!net || !q || !out) return nfail(net, SBLI_ERR_ARG, "sbli_net_forward: NULL argument");
+    if (batch < 1 || batch > net->max_batch)
+        return nfail(net, SBLI_ERR_ARG, "sbli_net_forward: batch must be in [1, %d]", net->max_batch);
+    int rc = forward_core(net, q, batch);
+    if (rc != SBLI_OK) return rc;
+    const int64_t NP = (int64_t)batch * net->P;
+    destandardize_kernel<<<nblk(NP), 256, 0, net->stream>>>(net->y, net->P, batch, net->stats + 10, out);
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+static int wgrad(sbli_net* net, int l, const __bf16* in, const __bf16* dout, int batch) {
+    const Layer& L = net->L[l];
+    const int64_t blocks = (int64_t)batch * net->n * net->n * (net->n / 32);
+    conv_wgrad_kernel<<<net->wgrad_wg, 256, 0, net->stream>>>(in, L.cpad, dout, L.opad, net->n, blocks, L.Kpad32,
+                                                              net->wpart);
+    wgrad_reduce_kernel<<<nblk(L.cout * L.cin * 27), 256, 0, net->stream>>>(net->wpart, net->wgrad_wg, L.Kpad32,
+                                                                           L.cpad, L.cin, L.cout,
+                                                                           net->grads + L.w_off);
+    bias_grad_kernel<<<L.cout, 256, 0, net->stream>>>(dout, L.opad, (int64_t)batch * net->P, net->grads + L.b_off);
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_gradients(sbli_net* net, const float* q, const float* target, int batch, double* loss) {
+    if (!net || !q || !target) return nfail(net, SBLI_ERR_ARG, "sbli_net_gradients: NULL argument");
+    if (batch < 1 || batch > net->max_batch)
+        return nfail(net, SBLI_ERR_ARG, "sbli_net_gradients: batch must be in [1, %d]", net->max_batch);
+    int rc = forward_core(net, q, batch);
+    if (rc != SBLI_OK) return rc;
+    const int64_t NP = (int64_t)batch * net->P;
+    const Layer* L = net->L;
+    const unsigned g = nblk(NP);
+    mse_grad_kernel<<<g, 256, 0, net->stream>>>(net->y, target, net->P, batch, net->stats + 10, net->dy, net->loss_part);
+    sum_doubles_kernel<<<1, 256, 0, net->stream>>>(net->loss_part, (int)g, 1.0 / (5.0 * (double)NP), net->loss);
+    // layer 3
+    if ((rc = wgrad(net, 2, net->h2, net->dy, batch)) != SBLI_OK) return rc;
+    conv_mfma_kernel<kEpiDGelu><<<g, 256, 0, net->stream>>>(net->dy, L[2].opad, L[2].Wb, L[2].Kb, nullptr, net->n, NP,
+                                                            nullptr, net->d2, net->pre2, 32, 32);
+    // layer 2
+    if ((rc = wgrad(net, 1, net->h1, net->d2, batch)) != SBLI_OK) return rc;
+    conv_mfma_kernel<kEpiDGelu><<<g, 256, 0, net->stream>>>(net->d2, L[1].opad, L[1].Wb, L[1].Kb, nullptr, net->n, NP,
+                                                            nullptr, net->d1, net->pre1, 32, 32);
+    // layer 1
+    if ((rc = wgrad(net, 0, net->x, net->d1, batch)) != SBLI_OK) return rc;
+    NHIP_TRY(net, hipGetLastError());
+    if (loss) {
+        NHIP_TRY(net, hipMemcpyAsync(loss, net->loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    }
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_train_step(sbli_net* net, const float* q, const float* target, int batch, float lr,
+                                   double* loss) {
+    if (!net) return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_train_step: net is NULL");
+    if (!(lr > 0) || !std::isfinite(lr)) return nfail(net, SBLI_ERR_ARG, "sbli_net_train_step: lr must be > 0");
+    int rc = sbli_net_gradients(net, q, target, batch, nullptr);
+    if (rc != SBLI_OK) return rc;
+    net->adam_t += 1;
+    adam_kernel<<<nblk(net->nparams), 256, 0, net->stream>>>(net->params, net->grads, net->adam_m, net->adam_v,
+                                                             net->nparams, lr, 0.9f, 0.999f, 1e-8f, net->adam_t);
+    NHIP_TRY(net, hipGetLastError());
+    rc = pack_all(net);
+    if (rc != SBLI_OK) return rc;
+    if (loss) {
+        NHIP_TRY(net, hipMemcpyAsync(loss, net->loss, sizeof(double), hipMemcpyDeviceToHost, net->stream));
+        NHIP_TRY(net, hipStreamSynchronize(net->stream));
+    }
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_guard(sbli_net* net, const float* c, int* flag, unsigned* counters) {
+    if (!net || !c || !flag || !counters) return nfail(net, SBLI_ERR_ARG, "sbli_net_guard: NULL argument");
+    closure_guard_kernel<<<1, 1024, 0, net->stream>>>(c, net->P, net->stats + 20, flag, counters);
+    NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_n(const sbli_net* net) { return net ? net->n : SBLI_ERR_ARG; }
+
+extern "C" int sbli_box_filter(const void* fine, int dtype, int nf, int nfields, int ratio, float* coarse,
+                               int subtract, void* hip_stream) {
+    if (!fine || !coarse) return nfail(nullptr, SBLI_ERR_ARG, "sbli_box_filter: NULL pointer");
+    if (ratio < 2 || ratio % 2 || nf < 2 * ratio || nf % ratio || nfields < 1)
+        return nfail(nullptr, SBLI_ERR_ARG, "sbli_box_filter: need an even ratio >= 2 dividing nf >= 2 ratio");
+    if (dtype != SBLI_F64 && dtype != SBLI_F32) return nfail(nullptr, SBLI_ERR_ARG, "sbli_box_filter: bad dtype");
+    const int nc = nf / ratio;
+    const int64_t total = (int64_t)nc * nc * nc * nfields;
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (dtype == SBLI_F64)
+        box_filter_kernel<double><<<nblk(total), 256, 0, s>>>((const double*)fine, nf, nfields, ratio, coarse,
+                                                              subtract);
+    else
+        box_filter_kernel<float><<<nblk(total), 256, 0, s>>>((const float*)fine, nf, nfields, ratio, coarse,
+                                                             subtract);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "sbli_box_filter: %s", hipGetErrorString(e));
+    return SBLI_OK;
+}

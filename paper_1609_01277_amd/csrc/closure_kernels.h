@@ -1,0 +1,457 @@
+// Kernels of the learned closure: box filter, channel statistics, standardise,
+// BF16-MFMA implicit-GEMM 3x3x3 periodic convolution (forward, backward-data,
+// backward-weight), bias gradient, MSE, Adam, weight packing, guard.
+//
+// Activation layout: channel-last [batch][point][channel] (point = (z*n + y)*n + x),
+// channel count padded to a multiple of 8 so 8 consecutive channels are one
+// 16-byte load.  The contraction index of a convolution is kk = tap*Cpad + c with
+// tap = (dz+1)*9 + (dy+1)*3 + (dx+1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sbli {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
+
+constexpr int kNetLayers = 3;
+
+__device__ __forceinline__ float gelu_f(float v) { return 0.5f * v * (1.0f + erff(v * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float v) {
+    return 0.5f * (1.0f + erff(v * 0.70710678118654752f)) + v * 0.39894228040143268f * expf(-0.5f * v * v);
+}
+
+__device__ __forceinline__ int wrapn(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+// ---------------------------------------------------------------------------
+// Box filter: separable centred trapezoid of width ratio*h (weights 1/(2 ratio)
+// at +-ratio/2, 1/ratio in between), sampled at every ratio-th fine point.
+// One thread per coarse output point and field.  With subtract != 0 the result
+// is F(fine) - coarse (in place), e.g. F R_f - R_c for a closure target.
+template <typename Tin>
+__global__ void __launch_bounds__(256) box_filter_kernel(const Tin* __restrict__ fine, int nf, int nfields, int ratio,
+                                                         float* __restrict__ coarse, int subtract) {
+    const int nc = nf / ratio;
+    const int64_t Pc = (int64_t)nc * nc * nc;
+    const int64_t Pf = (int64_t)nf * nf * nf;
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= Pc * nfields) return;
+    const int f = (int)(id / Pc);
+    const int64_t pc = id % Pc;
+    const int xc = (int)(pc % nc), yc = (int)((pc / nc) % nc), zc = (int)(pc / ((int64_t)nc * nc));
+    const int h = ratio / 2;
+    const double wi = 1.0 / ratio, we = 0.5 / ratio;
+    const Tin* src = fine + (int64_t)f * Pf;
+    double acc = 0.0;
+    for (int dz = -h; dz <= h; ++dz) {
+        const double wz = (dz == -h || dz == h) ? we : wi;
+        const int z = wrapn(zc * ratio + dz, nf);
+        double accy = 0.0;
+        for (int dy = -h; dy <= h; ++dy) {
+            const double wy = (dy == -h || dy == h) ? we : wi;
+            const int y = wrapn(yc * ratio + dy, nf);
+            const Tin* row = src + ((int64_t)z * nf + y) * nf;
+            double accx = 0.0;
+            for (int dx = -h; dx <= h; ++dx) {
+                const double wx = (dx == -h || dx == h) ? we : wi;
+                accx += wx * (double)row[wrapn(xc * ratio + dx, nf)];
+            }
+            accy += wy * accx;
+        }
+        acc += wz * accy;
+    }
+    const int64_t o = (int64_t)f * Pc + pc;
+    coarse[o] = subtract ? (float)(acc - (double)coarse[o]) : (float)acc;
+}
+
+// ---------------------------------------------------------------------------
+// Per-channel mean and standard deviation of `count` planar [5][P] FP32 arrays
+// (population statistics, FP64 sums).  One block per channel.
+__global__ void __launch_bounds__(256) channel_stats_kernel(const float* __restrict__ data, int count, int64_t P,
+                                                            float* __restrict__ mean_std /* [5] mean, [5] std */) {
+    const int c = blockIdx.x;
+    double s = 0.0, s2 = 0.0;
+    for (int b = 0; b < count; ++b) {
+        const float* src = data + ((int64_t)b * 5 + c) * P;
+        for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
+            const double v = src[i];
+            s += v;
+            s2 += v * v;
+        }
+    }
+    __shared__ double ss[256], ss2[256];
+    ss[threadIdx.x] = s;
+    ss2[threadIdx.x] = s2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            ss[threadIdx.x] += ss[threadIdx.x + w];
+            ss2[threadIdx.x] += ss2[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double N = (double)count * (double)P;
+        const double m = ss[0] / N;
+        const double var = ss2[0] / N - m * m;
+        mean_std[c] = (float)m;
+        mean_std[5 + c] = (float)sqrt(var > 0.0 ? var : 0.0);
+    }
+}
+
+// Planar FP32 [B][5][P] -> standardised channel-last BF16 [B][P][8] (channels 5..7 zero).
+__global__ void __launch_bounds__(256) standardize_kernel(const float* __restrict__ q, int64_t P, int B,
+                                                          const float* __restrict__ mean_std,
+                                                          __bf16* __restrict__ x) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)B * P) return;
+    const int64_t b = id / P, p = id % P;
+    bf16x8 v;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        float f = 0.0f;
+        if (c < 5) f = (q[(b * 5 + c) * P + p] - mean_std[c]) / mean_std[5 + c];
+        v[c] = (__bf16)f;
+    }
+    *(bf16x8*)(x + id * 8) = v;
+}
+
+// Network output y [B][P][8] (standardised) -> closure term planar [B][5][P].
+__global__ void __launch_bounds__(256) destandardize_kernel(const float* __restrict__ y, int64_t P, int B,
+                                                            const float* __restrict__ mean_std,
+                                                            float* __restrict__ out) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)B * P) return;
+    const int64_t b = id / P, p = id % P;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) out[(b * 5 + c) * P + p] = y[id * 8 + c] * mean_std[5 + c] + mean_std[c];
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM convolution on MFMA (v_mfma_f32_32x32x16_bf16).
+//   out[b][p][o] = sum_kk W[o][kk] * in[b][p + off(tap(kk))][c(kk)]
+// A wave computes 2 tiles of 32 points x 32 output channels; a workgroup of 4
+// waves covers 256 consecutive points.  A operand (points x 16 kk): each lane
+// loads 8 consecutive channels of one tap at one point (16 bytes); B operand
+// (16 kk x 32 outputs): 8 consecutive kk of one output channel (16 bytes) from
+// the packed weights Wp[32][Kpad].
+// Epilogues:
+//   kEpiGelu   : v = acc + bias; pre[..][o] = v (FP32, 32 ch); act[..][o] = bf16(gelu v)
+//   kEpiLinear : v = acc + bias; y[..][o] = v (FP32, ostride ch) for o < ocount
+//   kEpiDGelu  : v = acc * gelu'(pre[..][o]); act[..][o] = bf16(v) (32 ch)
+enum { kEpiGelu = 0, kEpiLinear = 1, kEpiDGelu = 2 };
+
+template <int EPI>
+__global__ void __launch_bounds__(256) conv_mfma_kernel(const __bf16* __restrict__ in, int cpad,
+                                                        const __bf16* __restrict__ Wp, int Kpad,
+                                                        const float* __restrict__ bias, int n, int64_t npts,
+                                                        float* __restrict__ fout, __bf16* __restrict__ bout,
+                                                        const float* __restrict__ pre_in, int ocount, int ostride) {
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int64_t P = (int64_t)n * n * n;
+    const int64_t base = (int64_t)blockIdx.x * 256 + wave * 64;
+    const int row = lane & 31;       // point within an M tile (A) / output channel (B)
+    const int half = lane >> 5;      // which 8 of the 16 kk this lane supplies
+    int px[2], py[2], pz[2];
+    int64_t pb[2];                   // b * P (sample base)
+    bool valid[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t g = base + t * 32 + row;
+        valid[t] = g < npts;
+        const int64_t gg = valid[t] ? g : 0;
+        pb[t] = (gg / P) * P;
+        const int64_t p = gg % P;
+        px[t] = (int)(p % n);
+        py[t] = (int)((p / n) % n);
+        pz[t] = (int)(p / ((int64_t)n * n));
+    }
+    floatx16 acc0 = {0}, acc1 = {0};
+    const __bf16* wrow = Wp + (int64_t)row * Kpad;
+    const int ntap_k = 27 * cpad;
+    for (int k0 = 0; k0 < Kpad; k0 += 16) {
+        const int kk = k0 + half * 8;
+        const bf16x8 bv = *(const bf16x8*)(wrow + kk);
+        bf16x8 a0, a1;
+        if (kk < ntap_k) {
+            const int tap = kk / cpad, c = kk % cpad;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int64_t q0 = pb[0] + ((int64_t)wrapn(pz[0] + dz, n) * n + wrapn(py[0] + dy, n)) * n + wrapn(px[0] + dx, n);
+            const int64_t q1 = pb[1] + ((int64_t)wrapn(pz[1] + dz, n) * n + wrapn(py[1] + dy, n)) * n + wrapn(px[1] + dx, n);
+            a0 = *(const bf16x8*)(in + q0 * cpad + c);
+            a1 = *(const bf16x8*)(in + q1 * cpad + c);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) { a0[j] = (__bf16)0.0f; a1[j] = (__bf16)0.0f; }
+        }
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bv, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bv, acc1, 0, 0, 0);
+    }
+    // D[m][o]: o = lane & 31, m = (j / 4) * 8 + (lane >> 5) * 4 + (j & 3)
+    const int o = row;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const floatx16 acc = t == 0 ? acc0 : acc1;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int m = (j / 4) * 8 + half * 4 + (j & 3);
+            const int64_t g = base + t * 32 + m;
+            if (g >= npts) continue;
+            if (EPI == kEpiGelu) {
+                const float v = acc[j] + bias[o];
+                fout[g * 32 + o] = v;
+                bout[g * 32 + o] = (__bf16)gelu_f(v);
+            } else if (EPI == kEpiLinear) {
+                if (o < ocount) fout[g * ostride + o] = acc[j] + bias[o];
+            } else {
+                bout[g * 32 + o] = (__bf16)(acc[j] * gelu_grad_f(pre_in[g * 32 + o]));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient on MFMA:  dW[o][kk] = sum_p dout[p][o] * in[p + off(tap)][c]
+// (o < 32 rows, kk < Kpad32 columns).  A workgroup takes blocks of 32
+// consecutive x-points of one (b, y, z) row (n % 32 == 0).  Per block it stages
+// in LDS, transposed so the reduction over points is contiguous:
+//   sd[o][32]                       dout of the block
+//   si[tap][c][32]                  input shifted by each of the 27 taps
+// then each wave accumulates its share of the Kpad32/32 column tiles.
+// Results: per-workgroup partial sums part[wg][32][Kpad32] (FP32).
+constexpr int kWgradMaxTiles = 28;   // Kpad32 / 32 <= 28 (27 * 32 = 864)
+
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(const __bf16* __restrict__ in, int cpad,
+                                                         const __bf16* __restrict__ dout, int opad, int n,
+                                                         int64_t nblocks, int Kpad32, float* __restrict__ part) {
+    __shared__ __attribute__((aligned(16))) __bf16 sd[32][32];
+    __shared__ __attribute__((aligned(16))) __bf16 si[27 * 32][32];   // [(tap * cpad + c)][point]
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int row = lane & 31, half = lane >> 5;
+    const int ntiles = Kpad32 / 32;
+    const int nrows = n / 32;            // 32-point blocks per x-row
+    const int64_t P = (int64_t)n * n * n;
+    floatx16 acc[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        for (int j = 0; j < 16; ++j) acc[i][j] = 0.0f;
+    const int64_t per = (nblocks + gridDim.x - 1) / gridDim.x;
+    const int64_t blk0 = (int64_t)blockIdx.x * per;
+    const int64_t blk1 = blk0 + per < nblocks ? blk0 + per : nblocks;
+    for (int64_t blk = blk0; blk < blk1; ++blk) {
+        // decode block -> (b, z, y, x0)
+        const int xb = (int)(blk % nrows);
+        const int64_t r = blk / nrows;
+        const int y = (int)(r % n);
+        const int z = (int)((r / n) % n);
+        const int64_t b = r / ((int64_t)n * n);
+        const int x0 = xb * 32;
+        __syncthreads();   // previous block's LDS reads are done
+        // stage dout: 32 points x opad channels (opad / 8 loads of 8 channels per point)
+        for (int t = threadIdx.x; t < 32 * (opad / 8); t += blockDim.x) {
+            const int pt = t % 32, cg = t / 32;
+            const int64_t g = b * P + ((int64_t)z * n + y) * n + x0 + pt;
+            const bf16x8 v = *(const bf16x8*)(dout + g * opad + cg * 8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) sd[cg * 8 + j][pt] = v[j];
+        }
+        for (int t = threadIdx.x + opad * 32; t < 32 * 32; t += blockDim.x) sd[t / 32][t % 32] = (__bf16)0.0f;
+        // stage the input for every tap
+        for (int t = threadIdx.x; t < 27 * 32 * (cpad / 8); t += blockDim.x) {
+            const int pt = t % 32;
+            const int rest = t / 32;
+            const int cg = rest % (cpad / 8);
+            const int tap = rest / (cpad / 8);
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int64_t g = b * P + ((int64_t)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x0 + pt + dx, n);
+            const bf16x8 v = *(const bf16x8*)(in + g * cpad + cg * 8);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) si[tap * cpad + cg * 8 + j][pt] = v[j];
+        }
+        __syncthreads();
+        // A[o][pts] from sd, B[pts][kk] from si; two k-steps of 16 points
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+            const bf16x8 av = *(const bf16x8*)(&sd[row][ks * 16 + half * 8]);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+                const int tile = wave + 4 * i;
+                if (tile < ntiles) {
+                    const int kk = tile * 32 + row;
+                    bf16x8 bv;
+                    if (kk < 27 * cpad) {
+                        bv = *(const bf16x8*)(&si[kk][ks * 16 + half * 8]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 8; ++j) bv[j] = (__bf16)0.0f;
+                    }
+                    acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // D[o][kk]: kk = tile*32 + (lane & 31), o = (j/4)*8 + half*4 + (j&3)
+    float* dst = part + (int64_t)blockIdx.x * 32 * Kpad32;
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+        const int tile = wave + 4 * i;
+        if (tile >= ntiles) continue;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int o = (j / 4) * 8 + half * 4 + (j & 3);
+            dst[(int64_t)o * Kpad32 + tile * 32 + row] = acc[i][j];
+        }
+    }
+}
+
+// Sums the per-workgroup partials in a fixed order and writes the gradient of
+// a layer in the master layout dW[o][c][tap] (o < cout, c < cin).
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nwg, int Kpad32,
+                                                           int cpad, int cin, int cout, float* __restrict__ dW) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    const int total = cout * cin * 27;
+    if (id >= total) return;
+    const int tap = id % 27;
+    const int c = (id / 27) % cin;
+    const int o = id / (27 * cin);
+    const int kk = tap * cpad + c;
+    float s = 0.0f;
+    for (int w = 0; w < nwg; ++w) s += part[((int64_t)w * 32 + o) * Kpad32 + kk];
+    dW[id] = s;
+}
+
+// Bias gradient db[o] = sum_p dout[p][o] (one block per output channel).
+__global__ void __launch_bounds__(256) bias_grad_kernel(const __bf16* __restrict__ dout, int opad, int64_t npts,
+                                                        float* __restrict__ db) {
+    const int o = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t p = threadIdx.x; p < npts; p += blockDim.x) s += (float)dout[p * opad + o];
+    __shared__ float ss[256];
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) ss[threadIdx.x] += ss[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) db[o] = ss[0];
+}
+
+// MSE between the network output y [B][P][8] (5 used) and the standardised
+// target (planar [B][5][P], standardised here): loss partial sums per block and
+// the BF16 gradient dy = 2 (y - t) / (5 B P) into [B][P][8].
+__global__ void __launch_bounds__(256) mse_grad_kernel(const float* __restrict__ y, const float* __restrict__ target,
+                                                       int64_t P, int B, const float* __restrict__ mean_std,
+                                                       __bf16* __restrict__ dy, double* __restrict__ loss_part) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const double scale = 2.0 / (5.0 * (double)B * (double)P);
+    double s = 0.0;
+    if (id < (int64_t)B * P) {
+        const int64_t b = id / P, p = id % P;
+        bf16x8 g;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            float gv = 0.0f;
+            if (c < 5) {
+                const float t = (target[(b * 5 + c) * P + p] - mean_std[c]) / mean_std[5 + c];
+                const float d = y[id * 8 + c] - t;
+                s += (double)d * d;
+                gv = (float)(scale * d);
+            }
+            g[c] = (__bf16)gv;
+        }
+        *(bf16x8*)(dy + id * 8) = g;
+    }
+    __shared__ double ss[256];
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) ss[threadIdx.x] += ss[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss_part[blockIdx.x] = ss[0];
+}
+
+__global__ void __launch_bounds__(256) sum_doubles_kernel(const double* __restrict__ part, int n, double scale,
+                                                          double* __restrict__ out) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += part[i];
+    __shared__ double ss[256];
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) ss[threadIdx.x] += ss[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = ss[0] * scale;
+}
+
+// Adam (Kingma & Ba) on a flat FP32 parameter vector; step t >= 1.
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int n, float lr,
+                                                   float beta1, float beta2, float eps, int t) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+    const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / (1.0f - powf(beta1, (float)t));
+    const float vh = vi / (1.0f - powf(beta2, (float)t));
+    p[i] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// Packs one layer's master weights W[o][c][tap] (FP32) into the MFMA layouts:
+//   Wf[o][tap*cpad + c]  (32 x Kf, forward),  Wb[c][tap'*opad + o] (32 x Kb,
+//   backward-data, tap' = 26 - tap mirrors the offset).  Padding entries are 0.
+__global__ void __launch_bounds__(256) pack_weights_kernel(const float* __restrict__ W, int cin, int cout, int cpad,
+                                                           int opad, int Kf, int Kb, __bf16* __restrict__ Wf,
+                                                           __bf16* __restrict__ Wb) {
+    const int id = blockIdx.x * blockDim.x + threadIdx.x;
+    if (id < 32 * Kf) {
+        const int o = id / Kf, kk = id % Kf;
+        const int tap = kk / cpad, c = kk % cpad;
+        float v = 0.0f;
+        if (o < cout && tap < 27 && c < cin) v = W[(o * cin + c) * 27 + tap];
+        Wf[id] = (__bf16)v;
+    }
+    if (id < 32 * Kb) {
+        const int c = id / Kb, kk = id % Kb;
+        const int tapm = kk / opad, o = kk % opad;
+        float v = 0.0f;
+        if (c < cin && tapm < 27 && o < cout) v = W[(o * cin + c) * 27 + (26 - tapm)];
+        Wb[id] = (__bf16)v;
+    }
+}
+
+// Closure guard: flag[0] = 1 if every closure value is finite and within
+// +-limit[f] for its field, else 0; counters[0|1] count accepted / rejected.
+__global__ void __launch_bounds__(1024) closure_guard_kernel(const float* __restrict__ C, int64_t P,
+                                                             const float* __restrict__ limit, int* __restrict__ flag,
+                                                             unsigned* __restrict__ counters) {
+    int bad = 0;
+    for (int f = 0; f < 5; ++f) {
+        const float L = limit[f];
+        for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
+            const float v = C[(int64_t)f * P + i];
+            bad |= !(fabsf(v) <= L);
+        }
+    }
+    __shared__ int sb[1024];
+    sb[threadIdx.x] = bad;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sb[threadIdx.x] |= sb[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        flag[0] = sb[0] ? 0 : 1;
+        atomicAdd(&counters[sb[0] ? 1 : 0], 1u);
+    }
+}
+
+}  // namespace sbli

@@ -137,10 +137,12 @@ struct DirSums {
 // PRE selects how far global loads run ahead of their use: 0 = loaded where used,
 // 1 = the state of the next plane and the next u-ring point are requested one
 // iteration early, 2 = dq of the next output plane as well.
+// clos (may be null): a closure term with the state's planar layout, added to
+// the residual when *cflag != 0.
 template <typename T, int R, int TX, int TY, int MODE, int PRE>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
-                                                 T B) {
+                                                 T B, const T* __restrict__ clos, const int* __restrict__ cflag) {
     using S = FusedShape<R, TX, TY>;
     __shared__ T s_u[3][S::BY2][S::BX2];
     __shared__ T s_pl[kPlFields][S::BY1][S::BX1];
@@ -392,7 +394,11 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             }
             if (store) {
                 const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
-                const T Rv[5] = {Rr, R0, R1, R2, RE};
+                T Rv[5] = {Rr, R0, R1, R2, RE};
+                if (clos != nullptr && cflag[0] != 0) {
+#pragma unroll
+                    for (int f = 0; f < 5; ++f) Rv[f] += clos[f * P + idx];
+                }
                 const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
 #pragma unroll
                 for (int f = 0; f < 5; ++f) {
@@ -420,6 +426,8 @@ struct BoxInst {
     int tiles_x, tiles_y, zchunk;
     int first_wg;      // first logical workgroup of this box
     int num_wg;        // tiles_x * tiles_y * ceil(nz / zchunk)
+    const T* closure;  // closure term of this box (planar, 5 fields) or null
+    const int* cflag;  // the closure is added only while *cflag != 0
 };
 
 // One launch covers `ninst` boxes (one for a single solver, many for an
@@ -450,7 +458,7 @@ __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
     const int zc = min(b.zchunk, b.c.n[2] - z0);
     T* dqb = dq ? dq + b.offset : nullptr;
     fused_stage_body<T, R, TX, TY, MODE, PRE>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
-                                              b.dt * dt_scale, A, B);
+                                              b.dt * dt_scale, A, B, b.closure, b.cflag);
 }
 
 }  // namespace sbli

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/sbli.h"
+#include "../../include/sbli_closure.h"
 #include "kernels_pointwise.h"
 #include "stage_variants.h"
 #include "stencil_weights.h"
@@ -31,6 +32,10 @@ struct sbli_ctx {
     BoxInst<double> inst64; // launch table entry (host copy) of the box
     BoxInst<float> inst32;
     void* inst_dev;         // the same entry on the device
+    sbli_net* net;          // attached closure network (FP32 solvers) or null
+    float* clos;            // closure term of the current stage (5 planar fields)
+    int* cflag;             // guard verdict for clos
+    unsigned* ccount;       // accepted / rejected closure evaluations
     double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
     double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
     double* diag_out;       // 10 doubles
@@ -106,6 +111,8 @@ static hipError_t update_table(sbli_ctx* x) {
         x->inst64.c = x->c64;
         x->inst64.offset = 0;
         x->inst64.dt = 1.0;
+        x->inst64.closure = nullptr;
+        x->inst64.cflag = nullptr;
         set_box_geometry(x->inst64, v.tx, v.ty, x->zchunk, 0);
         hipError_t e = hipMemcpyAsync(x->inst_dev, &x->inst64, sizeof(x->inst64), hipMemcpyHostToDevice, x->stream);
         return e == hipSuccess ? hipStreamSynchronize(x->stream) : e;
@@ -113,6 +120,8 @@ static hipError_t update_table(sbli_ctx* x) {
     x->inst32.c = x->c32;
     x->inst32.offset = 0;
     x->inst32.dt = 1.0f;
+    x->inst32.closure = x->net ? x->clos : nullptr;
+    x->inst32.cflag = x->net ? x->cflag : nullptr;
     set_box_geometry(x->inst32, v.tx, v.ty, x->zchunk, 0);
     hipError_t e = hipMemcpyAsync(x->inst_dev, &x->inst32, sizeof(x->inst32), hipMemcpyHostToDevice, x->stream);
     return e == hipSuccess ? hipStreamSynchronize(x->stream) : e;
@@ -198,6 +207,9 @@ extern "C" int sbli_destroy(sbli_ctx* ctx) {
     hipFree(ctx->diag_da);
     hipFree(ctx->diag_out);
     hipFree(ctx->inst_dev);
+    hipFree(ctx->clos);
+    hipFree(ctx->cflag);
+    hipFree(ctx->ccount);
     delete ctx;
     return SBLI_OK;
 }
@@ -253,6 +265,11 @@ static void* enqueue_steps(sbli_ctx* ctx, void* a, void* b, void* dq, double dt,
     void* dst = b;
     for (int s = 0; s < nsteps; ++s) {
         for (int k = 0; k < 3; ++k) {
+            if (ctx->net) {
+                // closure term of this stage's state, then its guard verdict
+                sbli_net_forward(ctx->net, (const float*)src, 1, ctx->clos);
+                sbli_net_guard(ctx->net, ctx->clos, ctx->cflag, ctx->ccount);
+            }
             launch_any(ctx, src, dq, dst, kModeStage1 + k, dt, kRK_A[k], kRK_B[k]);
             void* t = src;
             src = dst;
@@ -730,5 +747,35 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
     if (rc != SBLI_OK) return bfail(b, rc, "sbli_batch_autotune: a timing run failed");
     if (rc2 != SBLI_OK) return rc2;
     if (best_ms) *best_ms = best / reps;
+    return SBLI_OK;
+}
+
+extern "C" int sbli_closure_attach(sbli_ctx* ctx, sbli_net* net) {
+    if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_closure_attach: ctx is NULL");
+    if (net) {
+        if (ctx->p.dtype != SBLI_F32)
+            return fail(ctx, SBLI_ERR_ARG, "sbli_closure_attach: the closure needs an FP32 solver");
+        const int n = sbli_net_n(net);
+        if (ctx->p.nx != n || ctx->p.ny != n || ctx->p.nz != n)
+            return fail(ctx, SBLI_ERR_ARG, "sbli_closure_attach: grid %dx%dx%d does not match the network's %d^3",
+                        ctx->p.nx, ctx->p.ny, ctx->p.nz, n);
+        if (!ctx->clos) {
+            HIP_TRY(ctx, hipMalloc((void**)&ctx->clos, sizeof(float) * 5 * (size_t)npoints(ctx)));
+            HIP_TRY(ctx, hipMalloc((void**)&ctx->cflag, sizeof(int)));
+            HIP_TRY(ctx, hipMalloc((void**)&ctx->ccount, 2 * sizeof(unsigned)));
+            HIP_TRY(ctx, hipMemsetAsync(ctx->ccount, 0, 2 * sizeof(unsigned), ctx->stream));
+        }
+    }
+    ctx->net = net;
+    HIP_TRY(ctx, update_table(ctx));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_closure_counts(sbli_ctx* ctx, unsigned counts[2]) {
+    if (!ctx || !counts) return fail(ctx, SBLI_ERR_ARG, "sbli_closure_counts: NULL argument");
+    counts[0] = counts[1] = 0;
+    if (!ctx->ccount) return SBLI_OK;
+    HIP_TRY(ctx, hipMemcpyAsync(counts, ctx->ccount, 2 * sizeof(unsigned), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
     return SBLI_OK;
 }

@@ -75,3 +75,18 @@ def batch_instances(count=64, seed=1609, sizes=(32, 48, 64, 96, 128), re=(400.0,
         dt = courant * h / (1.0 + 1.0 / M)
         out.append(dict(n=n, Re=Re, Mach=M, Pr=pr, gamma=gamma, dt=dt, phase=phase))
     return out
+
+
+def closure_init_params(seed, channels=(5, 32, 32, 5)):
+    """Initial closure-network parameters from a seed, flat float32 vector.
+
+    Per layer W[out][in][3][3][3] ~ U(-b, b) with b = sqrt(6 / (27 in)) (He-uniform
+    for a 3x3x3 kernel), then zero biases; layers back to back.
+    """
+    rng = np.random.default_rng(seed)
+    parts = []
+    for ci, co in zip(channels[:-1], channels[1:]):
+        bound = math.sqrt(6.0 / (ci * 27))
+        parts.append(rng.uniform(-bound, bound, co * ci * 27))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)

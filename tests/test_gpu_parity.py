@@ -89,6 +89,23 @@ def test_rk3_tgv32_every_step(oracle_mod, order):
     print("max relative error over 10 steps: %.3e" % worst)
 
 
+@pytest.mark.parametrize("order", [4, 8])
+def test_rk3_tgv32_fp32_form(order):
+    """FP32 state: 10 steps of 32^3 Taylor-Green against the FP64 oracle.  Stated
+    tolerance 1e-5 relative per field (FP32 rounding of the stencil sums)."""
+    sbli, torch = _sbli()
+    n, dt = 32, 3.385e-3
+    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
+    qo = oracle.tgv_init(p)
+    s = sbli.Solver(n, order=order, dtype="f32", **synth.TGV)
+    q = to_dev(torch, qo, torch.float32)
+    qo = oracle.rk3(qo, p, dt, 10)
+    s.rk3_step(q, s.empty_state(), s.empty_state(), dt, 10)
+    errs = rel_err(q.cpu().numpy().astype(np.float64), qo)
+    print("FP32 order %d max relative error after 10 steps: %s" % (order, errs))
+    assert max(errs) <= 1e-5, errs
+
+
 def test_rk3_multi_step_call_equals_single_steps(oracle_mod):
     """One call with nsteps = 4 (even: no final copy) and nsteps = 3 (odd) vs the oracle."""
     sbli, torch = _sbli()
