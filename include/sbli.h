@@ -126,13 +126,14 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
 
 /*
  * Launch tuning of the fused stage kernel.  Each (dtype, order) has a small set
- * of compiled variants (x/y tile of a workgroup and how far the global loads
- * run ahead); together with the number of z-planes per workgroup ("zchunk") they
+ * of compiled variants (x/y tile of a workgroup, how far the global loads
+ * run ahead, how the register window advances); together with the number of z-planes per workgroup ("zchunk") they
  * fix the launch configuration.  All variants compute bitwise identical
  * results; only speed differs.
  *
  * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
- * sbli_variant_info: info = {tile x, tile y, load-ahead depth} of a variant.
+ * sbli_variant_info: info = {tile x, tile y, load-ahead depth, register-window
+ *   rotation (1) or shifting (0)} of a variant.
  * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
  *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).  sbli_set_tuning waits
  *   for the context's stream (it updates a small device table).
@@ -143,7 +144,7 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *   unspecified (they are advanced in time).  Synchronises the stream.
  */
 int sbli_num_variants(const sbli_ctx* ctx);
-int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]);
+int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[4]);
 int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk);
 int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk);
 int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms);

@@ -24,6 +24,9 @@
 // case beyond masking their stores.
 #pragma once
 
+#include <type_traits>
+#include <utility>
+
 #include "sbli_common.h"
 
 namespace sbli {
@@ -63,6 +66,16 @@ __device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T 
     s.p = gm1 * (E - T(0.5) * (m0 * s.u0 + m1 * s.u1 + m2 * s.u2));
     s.Tm = gM2 * s.p * rr;
     return s;
+}
+
+// Calls f(integral_constant<int, 0>), ..., f(integral_constant<int, N-1>).
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 __device__ __forceinline__ int wrap_mod(int v, int n) {
@@ -136,10 +149,11 @@ struct DirSums {
 // One workgroup = one (x, y) tile and one z-chunk [z0, z0 + zc).
 // PRE selects how far global loads run ahead of their use: 0 = loaded where used,
 // 1 = the state of the next plane and the next u-ring point are requested one
-// iteration early, 2 = dq of the next output plane as well.
+// iteration early, 2 = dq of the next output plane as well.  RT = 1 rotates the
+// register window instead of shifting it (for windows of at most 7 planes).
 // clos (may be null): a closure term with the state's planar layout, added to
 // the residual when *cflag != 0.
-template <typename T, int R, int TX, int TY, int MODE, int PRE>
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
                                                  T B, const T* __restrict__ clos, const int* __restrict__ cflag) {
@@ -211,7 +225,9 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     const int64_t ocol = (int64_t)wrap_mod(y0 + oy, ny) * nx + wrap_mod(x0 + ox, nx);
 
     // ---- register windows ----
-    PF<T> Qb[3 * R + 1];          // point fields, planes L-3R .. L (index 3R = newest)
+    constexpr int W = 3 * R + 1;
+    constexpr bool ROT = RT && W <= 7;  // rotate instead of shifting (code size grows W-fold)
+    PF<T> Qb[W];                  // point fields, planes L-3R .. L (logical index 3R = newest)
 #pragma unroll
     for (int s = 0; s <= 3 * R; ++s) Qb[s] = PF<T>{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
@@ -248,171 +264,188 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
         }
     };
     if (PRE > 0) issue(0);
-    for (int it = 0; it < iters; ++it) {
-        const int L = z0 - 2 * R + it;           // plane loaded this iteration
-        if (PRE == 0) issue(it);
-        const T cq0 = pq0, cq1 = pq1, cq2 = pq2, cq3 = pq3, cq4 = pq4;
-        const T cr0 = pr0, cr1 = pr1, cr2 = pr2, cr3 = pr3;
-        T cd[5] = {pd0, pd1, pd2, pd3, pd4};
-        if (PRE > 0 && it + 1 < iters) issue(it + 1);
-        // 1. plane L enters the window
-        if (e1) {
-            const PF<T> f = make_pf<T>(cq0, cq1, cq2, cq3, cq4, c.gm1, c.gM2);
-#pragma unroll
-            for (int s = 0; s < 3 * R; ++s) Qb[s] = Qb[s + 1];
-            Qb[3 * R] = f;
-        }
-        const bool do_grad = it >= 2 * R;
-        const bool do_out = it >= 4 * R;
-        // 2. LDS plane of u at the gradient plane a = L - R
-        if (do_grad) {
+    // One z-iteration.  With ROT the window is never shifted: logical plane k of
+    // the window lives in register slot (k + PH) % W, and the loop is unrolled W
+    // times so every slot index is a compile-time constant.
+    auto body = [&](auto ph, const int it) {
+        constexpr int PH = decltype(ph)::value;
+        auto slot = [](int k) { return ROT ? (k + PH) % W : k; };
+            const int L = z0 - 2 * R + it;           // plane loaded this iteration
+            if (PRE == 0) issue(it);
+            const T cq0 = pq0, cq1 = pq1, cq2 = pq2, cq3 = pq3, cq4 = pq4;
+            const T cr0 = pr0, cr1 = pr1, cr2 = pr2, cr3 = pr3;
+            T cd[5] = {pd0, pd1, pd2, pd3, pd4};
+            if (PRE > 0 && it + 1 < iters) issue(it + 1);
+            // 1. plane L enters the window
             if (e1) {
-                s_u[0][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u0;
-                s_u[1][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u1;
-                s_u[2][cy + 2 * R][cx + 2 * R] = Qb[2 * R].u2;
-            }
-            if (has_out) {
-                const T rr = T(1) / cr0;
-                s_u[0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
-                s_u[1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
-                s_u[2][oy + 2 * R][ox + 2 * R] = cr3 * rr;
-            }
-        }
-        __syncthreads();
-        // 3. velocity gradient at plane a -> nested fields; LDS plane of point fields at o
-        if (do_grad && e1) {
-            T g[3][3];
-#pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                T sx = 0, sy = 0, sz = 0;
-#pragma unroll
-                for (int m = 1; m <= R; ++m) {
-                    sx += c.da[0][m - 1] * (s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m]);
-                    sy += c.da[1][m - 1] * (s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R]);
-                    const T up = b == 0 ? Qb[2 * R + m].u0 : (b == 1 ? Qb[2 * R + m].u1 : Qb[2 * R + m].u2);
-                    const T um = b == 0 ? Qb[2 * R - m].u0 : (b == 1 ? Qb[2 * R - m].u1 : Qb[2 * R - m].u2);
-                    sz += c.da[2][m - 1] * (up - um);
+                const PF<T> f = make_pf<T>(cq0, cq1, cq2, cq3, cq4, c.gm1, c.gM2);
+                if (!ROT) {
+    #pragma unroll
+                    for (int s = 0; s < 3 * R; ++s) Qb[slot(s)] = Qb[slot(s + 1)];
                 }
-                g[b][0] = sx;
-                g[b][1] = sy;
-                g[b][2] = sz;
+                Qb[slot(3 * R)] = f;
             }
-            const T uc[3] = {Qb[2 * R].u0, Qb[2 * R].u1, Qb[2 * R].u2};
-            const T theta = g[0][0] + g[1][1] + g[2][2];
-            T V[3];
-#pragma unroll
-            for (int jj = 0; jj < 3; ++jj) {
-                T v = 0;
-#pragma unroll
-                for (int ii = 0; ii < 3; ++ii) {
-                    T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
-                    if (ii == jj) tau -= c.inv_Re23 * theta;
-                    v += uc[ii] * tau;
+            const bool do_grad = it >= 2 * R;
+            const bool do_out = it >= 4 * R;
+            // 2. LDS plane of u at the gradient plane a = L - R
+            if (do_grad) {
+                if (e1) {
+                    s_u[0][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u0;
+                    s_u[1][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u1;
+                    s_u[2][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u2;
                 }
-                V[jj] = v;
-            }
-            const int sxy = it % (R + 1);
-            s_axy[sxy][0][cy + R][cx + R] = V[0];
-            s_axy[sxy][1][cy + R][cx + R] = theta - g[0][0];
-            s_axy[sxy][2][cy + R][cx + R] = V[1];
-            s_axy[sxy][3][cy + R][cx + R] = theta - g[1][1];
-            if (interior) {
-                const int sz = it % (2 * R + 1);
-                s_az[sz][0][cy][cx] = V[2];
-                s_az[sz][1][cy][cx] = theta - g[2][2];
-            }
-        }
-        if (do_out && e1) {
-            const PF<T>& f = Qb[R];
-            const int ly = cy + R, lx = cx + R;
-            s_pl[0][ly][lx] = f.rho;
-            s_pl[1][ly][lx] = f.m0;
-            s_pl[2][ly][lx] = f.m1;
-            s_pl[3][ly][lx] = f.m2;
-            s_pl[4][ly][lx] = f.E;
-            s_pl[5][ly][lx] = f.u0;
-            s_pl[6][ly][lx] = f.u1;
-            s_pl[7][ly][lx] = f.u2;
-            s_pl[8][ly][lx] = f.p;
-            s_pl[9][ly][lx] = f.Tm;
-        }
-        __syncthreads();
-        // 4. residual and RK update at the output plane o = L - 2R
-        if (do_out && interior) {
-            const int ly = cy + R, lx = cx + R;
-            if (PRE < 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store) {
-                const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
-#pragma unroll
-                for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
-            }
-            auto ld = [&](int yy, int xx) {
-                PF<T> f;
-                f.rho = s_pl[0][yy][xx];
-                f.m0 = s_pl[1][yy][xx];
-                f.m1 = s_pl[2][yy][xx];
-                f.m2 = s_pl[3][yy][xx];
-                f.E = s_pl[4][yy][xx];
-                f.u0 = s_pl[5][yy][xx];
-                f.u1 = s_pl[6][yy][xx];
-                f.u2 = s_pl[7][yy][xx];
-                f.p = s_pl[8][yy][xx];
-                f.Tm = s_pl[9][yy][xx];
-                return f;
-            };
-            const PF<T>& s = Qb[R];
-            auto& axy = s_axy[(it - R) % (R + 1)];   // nested fields of plane o
-            T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
-            {
-                DirSums<T> ds;
-                ds.zero();
-#pragma unroll
-                for (int m = 1; m <= R; ++m)
-                    ds.template add<0>(ld(ly, lx + m), axy[0][ly][lx + m], axy[1][ly][lx + m], ld(ly, lx - m),
-                                       axy[0][ly][lx - m], axy[1][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
-                ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
-            }
-            {
-                DirSums<T> ds;
-                ds.zero();
-#pragma unroll
-                for (int m = 1; m <= R; ++m)
-                    ds.template add<1>(ld(ly + m, lx), axy[2][ly + m][lx], axy[3][ly + m][lx], ld(ly - m, lx),
-                                       axy[2][ly - m][lx], axy[3][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
-                ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
-            }
-            {
-                DirSums<T> ds;
-                ds.zero();
-#pragma unroll
-                for (int m = 1; m <= R; ++m)
-                    ds.template add<2>(Qb[R + m], s_az[(it + m - R) % (2 * R + 1)][0][cy][cx],
-                                       s_az[(it + m - R) % (2 * R + 1)][1][cy][cx], Qb[R - m],
-                                       s_az[(it - m - R) % (2 * R + 1)][0][cy][cx],
-                                       s_az[(it - m - R) % (2 * R + 1)][1][cy][cx],
-                                       c.da[2][m - 1], c.d2c[2][m - 1]);
-                ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
-            }
-            if (store) {
-                const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
-                T Rv[5] = {Rr, R0, R1, R2, RE};
-                if (clos != nullptr && cflag[0] != 0) {
-#pragma unroll
-                    for (int f = 0; f < 5; ++f) Rv[f] += clos[f * P + idx];
+                if (has_out) {
+                    const T rr = T(1) / cr0;
+                    s_u[0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
+                    s_u[1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
+                    s_u[2][oy + 2 * R][ox + 2 * R] = cr3 * rr;
                 }
-                const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
-#pragma unroll
-                for (int f = 0; f < 5; ++f) {
-                    if (MODE == kModeRHS) {
-                        out[f * P + idx] = Rv[f];
-                    } else {
-                        T dn = dt * Rv[f];
-                        if (MODE != kModeStage1) dn += A * cd[f];
-                        if (MODE != kModeStage3) dq[f * P + idx] = dn;
-                        out[f * P + idx] = qv[f] + B * dn;
+            }
+            __syncthreads();
+            // 3. velocity gradient at plane a -> nested fields; LDS plane of point fields at o
+            if (do_grad && e1) {
+                T g[3][3];
+    #pragma unroll
+                for (int b = 0; b < 3; ++b) {
+                    T sx = 0, sy = 0, sz = 0;
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m) {
+                        sx += c.da[0][m - 1] * (s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m]);
+                        sy += c.da[1][m - 1] * (s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R]);
+                        const T up = b == 0 ? Qb[slot(2 * R + m)].u0 : (b == 1 ? Qb[slot(2 * R + m)].u1 : Qb[slot(2 * R + m)].u2);
+                        const T um = b == 0 ? Qb[slot(2 * R - m)].u0 : (b == 1 ? Qb[slot(2 * R - m)].u1 : Qb[slot(2 * R - m)].u2);
+                        sz += c.da[2][m - 1] * (up - um);
+                    }
+                    g[b][0] = sx;
+                    g[b][1] = sy;
+                    g[b][2] = sz;
+                }
+                const T uc[3] = {Qb[slot(2 * R)].u0, Qb[slot(2 * R)].u1, Qb[slot(2 * R)].u2};
+                const T theta = g[0][0] + g[1][1] + g[2][2];
+                T V[3];
+    #pragma unroll
+                for (int jj = 0; jj < 3; ++jj) {
+                    T v = 0;
+    #pragma unroll
+                    for (int ii = 0; ii < 3; ++ii) {
+                        T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
+                        if (ii == jj) tau -= c.inv_Re23 * theta;
+                        v += uc[ii] * tau;
+                    }
+                    V[jj] = v;
+                }
+                const int sxy = it % (R + 1);
+                s_axy[sxy][0][cy + R][cx + R] = V[0];
+                s_axy[sxy][1][cy + R][cx + R] = theta - g[0][0];
+                s_axy[sxy][2][cy + R][cx + R] = V[1];
+                s_axy[sxy][3][cy + R][cx + R] = theta - g[1][1];
+                if (interior) {
+                    const int sz = it % (2 * R + 1);
+                    s_az[sz][0][cy][cx] = V[2];
+                    s_az[sz][1][cy][cx] = theta - g[2][2];
+                }
+            }
+            if (do_out && e1) {
+                const PF<T>& f = Qb[slot(R)];
+                const int ly = cy + R, lx = cx + R;
+                s_pl[0][ly][lx] = f.rho;
+                s_pl[1][ly][lx] = f.m0;
+                s_pl[2][ly][lx] = f.m1;
+                s_pl[3][ly][lx] = f.m2;
+                s_pl[4][ly][lx] = f.E;
+                s_pl[5][ly][lx] = f.u0;
+                s_pl[6][ly][lx] = f.u1;
+                s_pl[7][ly][lx] = f.u2;
+                s_pl[8][ly][lx] = f.p;
+                s_pl[9][ly][lx] = f.Tm;
+            }
+            __syncthreads();
+            // 4. residual and RK update at the output plane o = L - 2R
+            if (do_out && interior) {
+                const int ly = cy + R, lx = cx + R;
+                if (PRE < 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store) {
+                    const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+    #pragma unroll
+                    for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
+                }
+                auto ld = [&](int yy, int xx) {
+                    PF<T> f;
+                    f.rho = s_pl[0][yy][xx];
+                    f.m0 = s_pl[1][yy][xx];
+                    f.m1 = s_pl[2][yy][xx];
+                    f.m2 = s_pl[3][yy][xx];
+                    f.E = s_pl[4][yy][xx];
+                    f.u0 = s_pl[5][yy][xx];
+                    f.u1 = s_pl[6][yy][xx];
+                    f.u2 = s_pl[7][yy][xx];
+                    f.p = s_pl[8][yy][xx];
+                    f.Tm = s_pl[9][yy][xx];
+                    return f;
+                };
+                const PF<T>& s = Qb[slot(R)];
+                auto& axy = s_axy[(it - R) % (R + 1)];   // nested fields of plane o
+                T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
+                {
+                    DirSums<T> ds;
+                    ds.zero();
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m)
+                        ds.template add<0>(ld(ly, lx + m), axy[0][ly][lx + m], axy[1][ly][lx + m], ld(ly, lx - m),
+                                           axy[0][ly][lx - m], axy[1][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
+                    ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
+                }
+                {
+                    DirSums<T> ds;
+                    ds.zero();
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m)
+                        ds.template add<1>(ld(ly + m, lx), axy[2][ly + m][lx], axy[3][ly + m][lx], ld(ly - m, lx),
+                                           axy[2][ly - m][lx], axy[3][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
+                    ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
+                }
+                {
+                    DirSums<T> ds;
+                    ds.zero();
+    #pragma unroll
+                    for (int m = 1; m <= R; ++m)
+                        ds.template add<2>(Qb[slot(R + m)], s_az[(it + m - R) % (2 * R + 1)][0][cy][cx],
+                                           s_az[(it + m - R) % (2 * R + 1)][1][cy][cx], Qb[slot(R - m)],
+                                           s_az[(it - m - R) % (2 * R + 1)][0][cy][cx],
+                                           s_az[(it - m - R) % (2 * R + 1)][1][cy][cx],
+                                           c.da[2][m - 1], c.d2c[2][m - 1]);
+                    ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
+                }
+                if (store) {
+                    const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+                    T Rv[5] = {Rr, R0, R1, R2, RE};
+                    if (clos != nullptr && cflag[0] != 0) {
+    #pragma unroll
+                        for (int f = 0; f < 5; ++f) Rv[f] += clos[f * P + idx];
+                    }
+                    const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
+    #pragma unroll
+                    for (int f = 0; f < 5; ++f) {
+                        if (MODE == kModeRHS) {
+                            out[f * P + idx] = Rv[f];
+                        } else {
+                            T dn = dt * Rv[f];
+                            if (MODE != kModeStage1) dn += A * cd[f];
+                            if (MODE != kModeStage3) dq[f * P + idx] = dn;
+                            out[f * P + idx] = qv[f] + B * dn;
+                        }
                     }
                 }
             }
+    };
+    if constexpr (ROT) {
+        for (int it0 = 0; it0 < iters; it0 += W) {
+            static_for<W>([&](auto ph) {
+                const int it = it0 + decltype(ph)::value;
+                if (it < iters) body(ph, it);
+            });
         }
+    } else {
+        for (int it = 0; it < iters; ++it) body(std::integral_constant<int, 0>{}, it);
     }
 }
 
@@ -435,7 +468,7 @@ struct BoxInst {
 // by first_wg.  Workgroups are handed to the 8 XCDs round-robin by id; the id is
 // remapped so that each XCD (with its own L2) walks a contiguous run of
 // neighbouring tiles, whose halos then hit in that L2.
-template <typename T, int R, int TX, int TY, int MODE, int PRE>
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                        const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
@@ -457,7 +490,7 @@ __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
     const int z0 = chunk * b.zchunk;
     const int zc = min(b.zchunk, b.c.n[2] - z0);
     T* dqb = dq ? dq + b.offset : nullptr;
-    fused_stage_body<T, R, TX, TY, MODE, PRE>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
+    fused_stage_body<T, R, TX, TY, MODE, PRE, RT>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
                                               b.dt * dt_scale, A, B, b.closure, b.cflag);
 }
 

@@ -328,7 +328,7 @@ extern "C" int sbli_num_variants(const sbli_ctx* ctx) {
     return num_variants(ctx);
 }
 
-extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]) {
+extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[4]) {
     if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
     if (variant < 0 || variant >= num_variants(ctx))
         return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
@@ -336,6 +336,7 @@ extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[3]) 
     info[0] = v.tx;
     info[1] = v.ty;
     info[2] = v.pre;
+    info[3] = v.rot;
     return SBLI_OK;
 }
 
