@@ -48,11 +48,13 @@ int sbli_net_get_params(sbli_net* net, float* host_params);
 /* Host copy of the gradients left by the last sbli_net_gradients / train_step. */
 int sbli_net_get_grads(sbli_net* net, float* host_grads);
 
-/* Statistics, 25 floats: [0..4] input means, [5..9] input standard deviations,
+/* Statistics, 35 floats: [0..4] input means, [5..9] input standard deviations,
  * [10..14] output means, [15..19] output standard deviations, [20..24] per-field
- * guard limits on |C| (see sbli_net_guard).  sbli_net_channel_stats computes the
- * population mean and standard deviation per field of `count` planar samples
- * (FP64 sums) on the device into the input (which = 0) or output (which = 1) slots. */
+ * guard limits on |C| (see sbli_net_guard), [25..29] / [30..34] largest |value|
+ * per field of the input / output samples.  sbli_net_channel_stats computes the
+ * population mean, standard deviation (FP64 sums) and largest magnitude per
+ * field of `count` planar samples on the device into the input (which = 0) or
+ * output (which = 1) slots. */
 int sbli_net_set_stats(sbli_net* net, const float* host_stats);
 int sbli_net_get_stats(sbli_net* net, float* host_stats);
 int sbli_net_channel_stats(sbli_net* net, const float* data, int count, int which);

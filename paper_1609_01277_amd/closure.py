@@ -10,7 +10,7 @@ import numpy as np
 
 from . import _lib
 
-N_STATS = 25
+N_STATS = 35
 _ready = False
 
 

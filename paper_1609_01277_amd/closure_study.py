@@ -40,11 +40,12 @@ def main(argv=None):
     ap.add_argument("--t-end", type=float, default=10.0)
     ap.add_argument("--res", default="800,1600,3200")
     ap.add_argument("--snapshots", type=int, default=2000)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=16)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=1609)
-    ap.add_argument("--guard", type=float, default=20.0, help="limit = |mean| + guard * std per field")
+    ap.add_argument("--guard", type=float, default=2.0,
+                    help="guard limit per field = guard * (largest |C*| of that field in the training set)")
     ap.add_argument("--diag-every", type=int, default=10, help="coarse steps between diagnostics")
     args = ap.parse_args(argv)
 
@@ -106,7 +107,7 @@ def main(argv=None):
     net.channel_stats(X[:nsnap], 0)
     net.channel_stats(Y[:nsnap], 1)
     st = net.get_stats()
-    st[20:25] = np.abs(st[10:15]) + args.guard * st[15:20]
+    st[20:25] = args.guard * st[30:35]
     net.set_stats(st)
     out["stats"] = [float(v) for v in st]
     net.set_params(synth.closure_init_params(args.seed))

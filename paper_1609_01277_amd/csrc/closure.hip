@@ -38,7 +38,8 @@ struct sbli_net {
     int nparams = 0;
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     int adam_t = 0;
-    float* stats = nullptr;          // [0..9] input mean/std, [10..19] output mean/std, [20..24] guard limits
+    float* stats = nullptr;          // [0..9] input mean/std, [10..19] output mean/std, [20..24] guard
+                                     // limits, [25..29] input max |x|, [30..34] output max |x|
     __bf16 *x = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *d2 = nullptr, *d1 = nullptr;
     float *pre1 = nullptr, *pre2 = nullptr, *y = nullptr;
     float* wpart = nullptr;          // weight-gradient partials
@@ -128,7 +129,7 @@ extern "C" int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net*
     alloc((void**)&net->grads, sizeof(float) * net->nparams);
     alloc((void**)&net->adam_m, sizeof(float) * net->nparams);
     alloc((void**)&net->adam_v, sizeof(float) * net->nparams);
-    alloc((void**)&net->stats, sizeof(float) * 32);
+    alloc((void**)&net->stats, sizeof(float) * 40);
     alloc((void**)&net->x, sizeof(__bf16) * NP * 8);
     alloc((void**)&net->h1, sizeof(__bf16) * NP * 32);
     alloc((void**)&net->h2, sizeof(__bf16) * NP * 32);
@@ -149,7 +150,7 @@ extern "C" int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net*
         return e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP;
     }
     // identity standardisation until set: mean 0, std 1, no guard limit
-    float st[32] = {0};
+    float st[40] = {0};
     for (int c = 0; c < 5; ++c) {
         st[5 + c] = 1.0f;
         st[15 + c] = 1.0f;
@@ -215,7 +216,8 @@ extern "C" int sbli_net_channel_stats(sbli_net* net, const float* data, int coun
     if (!net || !data) return nfail(net, SBLI_ERR_ARG, "sbli_net_channel_stats: NULL argument");
     if (count < 1 || (which != 0 && which != 1))
         return nfail(net, SBLI_ERR_ARG, "sbli_net_channel_stats: count >= 1 and which in {0, 1} required");
-    channel_stats_kernel<<<5, 256, 0, net->stream>>>(data, count, net->P, net->stats + 10 * which);
+    channel_stats_kernel<<<5, 256, 0, net->stream>>>(data, count, net->P, net->stats + 10 * which,
+                                                    net->stats + 25 + 5 * which);
     NHIP_TRY(net, hipGetLastError());
     return SBLI_OK;
 }
@@ -225,14 +227,14 @@ extern "C" int sbli_net_set_stats(sbli_net* net, const float* host_stats) {
     for (int c = 0; c < 5; ++c)
         if (!(host_stats[5 + c] > 0) || !(host_stats[15 + c] > 0))
             return nfail(net, SBLI_ERR_ARG, "sbli_net_set_stats: standard deviations must be > 0");
-    NHIP_TRY(net, hipMemcpyAsync(net->stats, host_stats, sizeof(float) * 25, hipMemcpyHostToDevice, net->stream));
+    NHIP_TRY(net, hipMemcpyAsync(net->stats, host_stats, sizeof(float) * 35, hipMemcpyHostToDevice, net->stream));
     NHIP_TRY(net, hipStreamSynchronize(net->stream));
     return SBLI_OK;
 }
 
 extern "C" int sbli_net_get_stats(sbli_net* net, float* host_stats) {
     if (!net || !host_stats) return nfail(net, SBLI_ERR_ARG, "sbli_net_get_stats: NULL argument");
-    NHIP_TRY(net, hipMemcpyAsync(host_stats, net->stats, sizeof(float) * 25, hipMemcpyDeviceToHost, net->stream));
+    NHIP_TRY(net, hipMemcpyAsync(host_stats, net->stats, sizeof(float) * 35, hipMemcpyDeviceToHost, net->stream));
     NHIP_TRY(net, hipStreamSynchronize(net->stream));
     return SBLI_OK;
 }

@@ -67,28 +67,34 @@ __global__ void __launch_bounds__(256) box_filter_kernel(const Tin* __restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Per-channel mean and standard deviation of `count` planar [5][P] FP32 arrays
-// (population statistics, FP64 sums).  One block per channel.
+// Per-channel mean, standard deviation (population statistics, FP64 sums) and
+// largest magnitude of `count` planar [5][P] FP32 arrays.  One block per channel.
 __global__ void __launch_bounds__(256) channel_stats_kernel(const float* __restrict__ data, int count, int64_t P,
-                                                            float* __restrict__ mean_std /* [5] mean, [5] std */) {
+                                                            float* __restrict__ mean_std /* [5] mean, [5] std */,
+                                                            float* __restrict__ maxabs /* [5] */) {
     const int c = blockIdx.x;
     double s = 0.0, s2 = 0.0;
+    float mx = 0.0f;
     for (int b = 0; b < count; ++b) {
         const float* src = data + ((int64_t)b * 5 + c) * P;
         for (int64_t i = threadIdx.x; i < P; i += blockDim.x) {
             const double v = src[i];
             s += v;
             s2 += v * v;
+            mx = fmaxf(mx, fabsf(src[i]));
         }
     }
     __shared__ double ss[256], ss2[256];
+    __shared__ float sm[256];
     ss[threadIdx.x] = s;
     ss2[threadIdx.x] = s2;
+    sm[threadIdx.x] = mx;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             ss[threadIdx.x] += ss[threadIdx.x + w];
             ss2[threadIdx.x] += ss2[threadIdx.x + w];
+            sm[threadIdx.x] = fmaxf(sm[threadIdx.x], sm[threadIdx.x + w]);
         }
         __syncthreads();
     }
@@ -98,6 +104,7 @@ __global__ void __launch_bounds__(256) channel_stats_kernel(const float* __restr
         const double var = ss2[0] / N - m * m;
         mean_std[c] = (float)m;
         mean_std[5 + c] = (float)sqrt(var > 0.0 ? var : 0.0);
+        maxabs[c] = sm[0];
     }
 }
 

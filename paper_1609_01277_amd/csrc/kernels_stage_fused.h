@@ -51,6 +51,22 @@ struct PF {
     T rho, m0, m1, m2, E, u0, u1, u2, p, Tm;
 };
 
+// 1/x from the hardware reciprocal refined by Newton steps (two in FP64, one in
+// FP32): within an ulp of the quotient, at a third of the instructions of the
+// IEEE division sequence.
+__device__ __forceinline__ double fast_recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float fast_recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
 template <typename T>
 __device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T gM2) {
     PF<T> s;
@@ -59,7 +75,7 @@ __device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T 
     s.m1 = m1;
     s.m2 = m2;
     s.E = E;
-    const T rr = T(1) / rho;
+    const T rr = fast_recip(rho);
     s.u0 = m0 * rr;
     s.u1 = m1 * rr;
     s.u2 = m2 * rr;
@@ -295,7 +311,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     s_u[2][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u2;
                 }
                 if (has_out) {
-                    const T rr = T(1) / cr0;
+                    const T rr = fast_recip(cr0);
                     s_u[0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
                     s_u[1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
                     s_u[2][oy + 2 * R][ox + 2 * R] = cr3 * rr;

@@ -61,6 +61,9 @@ inline bool try_variant(int& k, int want, const StageArgs& a, const T* qin, T* d
 template <typename T, int R>
 struct VariantSet;
 
+// The launch function of a (type, radius) -- which instantiates its kernels --
+// is defined only in the translation unit stage_{f64,f32}_r{1..4}.hip that sets
+// SBLI_STAGE_TU_{TYPE,R,LIST}, so the variants compile in parallel.
 #define SBLI_VARIANT_SET(TYPE, RR, LIST)                                                                  \
     template <>                                                                                           \
     struct VariantSet<TYPE, RR> {                                                                         \
@@ -74,11 +77,7 @@ struct VariantSet;
             static const StageVariant t[] = {LIST(SBLI_ENTRY)};                                          \
             return t[i];                                                                                  \
         }                                                                                                 \
-        static bool launch(int v, const StageArgs& a, const T* qin, T* dq, T* qout) {                   \
-            int k = 0;                                                                                    \
-            LIST(SBLI_TRY)                                                                                \
-            return false;                                                                                 \
-        }                                                                                                 \
+        static bool launch(int v, const StageArgs& a, const T* qin, T* dq, T* qout);                  \
     };
 
 SBLI_VARIANT_SET(double, 1, SBLI_VARIANTS_D1)
@@ -90,6 +89,15 @@ SBLI_VARIANT_SET(float, 2, SBLI_VARIANTS_F2)
 SBLI_VARIANT_SET(float, 3, SBLI_VARIANTS_F3)
 SBLI_VARIANT_SET(float, 4, SBLI_VARIANTS_F4)
 
+#if defined(SBLI_STAGE_TU_TYPE) && defined(SBLI_STAGE_TU_R) && defined(SBLI_STAGE_TU_LIST)
+bool VariantSet<SBLI_STAGE_TU_TYPE, SBLI_STAGE_TU_R>::launch(int v, const StageArgs& a, const T* qin, T* dq,
+                                                             T* qout) {
+    int k = 0;
+    SBLI_STAGE_TU_LIST(SBLI_TRY)
+    return false;
+}
+#endif
+
 #undef SBLI_TRY
 #undef SBLI_ENTRY
 #undef SBLI_VARIANT_SET
@@ -97,31 +105,38 @@ SBLI_VARIANT_SET(float, 4, SBLI_VARIANTS_F4)
 // Runtime dispatch over (radius, variant) for one element type.
 template <typename T>
 struct StageDispatch {
-    static int count(int r) {
-        switch (r) {
-            case 1: return VariantSet<T, 1>::count();
-            case 2: return VariantSet<T, 2>::count();
-            case 3: return VariantSet<T, 3>::count();
-            default: return VariantSet<T, 4>::count();
-        }
-    }
-    static StageVariant get(int r, int i) {
-        switch (r) {
-            case 1: return VariantSet<T, 1>::get(i);
-            case 2: return VariantSet<T, 2>::get(i);
-            case 3: return VariantSet<T, 3>::get(i);
-            default: return VariantSet<T, 4>::get(i);
-        }
-    }
-    static bool launch(int r, int v, const StageArgs& a, const T* qin, T* dq, T* qout) {
-        switch (r) {
-            case 1: return VariantSet<T, 1>::launch(v, a, qin, dq, qout);
-            case 2: return VariantSet<T, 2>::launch(v, a, qin, dq, qout);
-            case 3: return VariantSet<T, 3>::launch(v, a, qin, dq, qout);
-            default: return VariantSet<T, 4>::launch(v, a, qin, dq, qout);
-        }
-    }
+    static int count(int r);
+    static StageVariant get(int r, int i);
+    static bool launch(int r, int v, const StageArgs& a, const T* qin, T* dq, T* qout);
 };
+
+template <typename T>
+inline int StageDispatch<T>::count(int r) {
+    switch (r) {
+        case 1: return VariantSet<T, 1>::count();
+        case 2: return VariantSet<T, 2>::count();
+        case 3: return VariantSet<T, 3>::count();
+        default: return VariantSet<T, 4>::count();
+    }
+}
+template <typename T>
+inline StageVariant StageDispatch<T>::get(int r, int i) {
+    switch (r) {
+        case 1: return VariantSet<T, 1>::get(i);
+        case 2: return VariantSet<T, 2>::get(i);
+        case 3: return VariantSet<T, 3>::get(i);
+        default: return VariantSet<T, 4>::get(i);
+    }
+}
+template <typename T>
+inline bool StageDispatch<T>::launch(int r, int v, const StageArgs& a, const T* qin, T* dq, T* qout) {
+    switch (r) {
+        case 1: return VariantSet<T, 1>::launch(v, a, qin, dq, qout);
+        case 2: return VariantSet<T, 2>::launch(v, a, qin, dq, qout);
+        case 3: return VariantSet<T, 3>::launch(v, a, qin, dq, qout);
+        default: return VariantSet<T, 4>::launch(v, a, qin, dq, qout);
+    }
+}
 
 // Fills the launch-geometry part of a box entry for tile (tx, ty) and zchunk;
 // returns the number of workgroups the box takes.

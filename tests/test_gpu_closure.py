@@ -45,7 +45,7 @@ def make_case(n=32, seed=0):
     t = (0.05 * rng.standard_normal((1, 5, n, n, n))).astype(np.float32)
     layers = nn.init_params(rng)
     layers = [(W, 0.1 * rng.standard_normal(b.shape)) for W, b in layers]
-    stats = np.zeros(25, dtype=np.float32)
+    stats = np.zeros(35, dtype=np.float32)
     stats[0:5] = q[0].reshape(5, -1).mean(axis=1)
     stats[5:10] = q[0].reshape(5, -1).std(axis=1)
     stats[10:15] = 0.01 * np.arange(5)
@@ -100,6 +100,7 @@ def test_channel_stats_and_guard():
     d = data.cpu().numpy()[0].reshape(5, -1).astype(np.float64)
     assert np.allclose(st[0:5], d.mean(axis=1), rtol=1e-6, atol=1e-7)
     assert np.allclose(st[5:10], d.std(axis=1), rtol=1e-5)
+    assert np.array_equal(st[25:30], np.abs(data.cpu().numpy()[0]).reshape(5, -1).max(axis=1))
     st[20:25] = 2.0
     st[15:20] = 1.0
     net.set_stats(st)
@@ -169,7 +170,7 @@ def test_closure_attach_constant_term_matches_oracle():
     b3 = np.array([0.5, -0.3, 0.2, 0.1, -0.4])
     layers[2] = (layers[2][0], b3)
     net.set_params(closure.join_params(layers).astype(np.float32))
-    stats = np.zeros(25, dtype=np.float32)
+    stats = np.zeros(35, dtype=np.float32)
     stats[5:10] = 1.0
     stats[10:15] = [0.1, 0.2, 0.0, -0.1, 0.3]
     stats[15:20] = 2.0
@@ -201,7 +202,7 @@ def test_closure_fallback_when_guard_rejects_or_detached():
     layers = [(np.zeros_like(W), np.zeros_like(b)) for W, b in nn.init_params(np.random.default_rng(0))]
     layers[2] = (layers[2][0], np.full(5, 0.7))
     net.set_params(closure.join_params(layers).astype(np.float32))
-    stats = np.zeros(25, dtype=np.float32)
+    stats = np.zeros(35, dtype=np.float32)
     stats[5:10] = 1.0
     stats[15:20] = 1.0
     stats[20:25] = 0.5            # |C| = 0.7 exceeds every limit: always rejected
