@@ -47,6 +47,8 @@ def main(argv=None):
     ap.add_argument("--guard", type=float, default=2.0,
                     help="guard limit per field = guard * (largest |C*| of that field in the training set)")
     ap.add_argument("--diag-every", type=int, default=10, help="coarse steps between diagnostics")
+    ap.add_argument("--hold-out", type=int, default=10,
+                    help="every n-th snapshot is held out of training for the a-priori test")
     args = ap.parse_args(argv)
 
     torch.cuda.set_device(0)
@@ -115,12 +117,14 @@ def main(argv=None):
     xb = torch.empty((args.batch, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
     yb = torch.empty_like(xb)
     losses = []
-    steps_per_epoch = nsnap // args.batch
+    held = np.arange(0, nsnap, args.hold_out) if args.hold_out > 0 else np.zeros(0, dtype=int)
+    train_idx = np.setdiff1d(np.arange(nsnap), held)
+    steps_per_epoch = len(train_idx) // args.batch
     flop_per_sample = 2 * Pc * 27 * (8 * 32 + 32 * 32 + 32 * 32) * 3   # fwd + bwd-data + bwd-weight, padded
     t1 = time.time()
     torch.cuda.synchronize()
     for ep in range(args.epochs):
-        perm = rng.permutation(nsnap)
+        perm = train_idx[rng.permutation(len(train_idx))]
         tot = 0.0
         for s in range(steps_per_epoch):
             idx = perm[s * args.batch:(s + 1) * args.batch]
@@ -148,6 +152,26 @@ def main(argv=None):
     ms = e0.elapsed_time(e1) / 10
     out["training"]["fwd_bwd_ms_per_batch"] = ms
     out["training"]["fwd_bwd_padded_tflops_per_s"] = flop_per_sample * args.batch / (ms * 1e-3) / 1e12
+
+    # ---- a-priori: the closure term on held-out snapshots ----
+    # relative L2 error of the predicted closure term against C*, per field; the
+    # method without the closure predicts C = 0, i.e. a relative error of 1
+    num = np.zeros(5)
+    den = np.zeros(5)
+    pred = torch.empty((1, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
+    for i in held:
+        net.forward(X[int(i)][None], pred)
+        d = (pred[0].double() - Y[int(i)].double()).reshape(5, -1)
+        num += (d * d).sum(dim=1).cpu().numpy()
+        den += (Y[int(i)].double().reshape(5, -1) ** 2).sum(dim=1).cpu().numpy()
+    if len(held):
+        rel = np.sqrt(num / np.maximum(den, 1e-300))
+        out["a_priori"] = {"held_out_snapshots": int(len(held)),
+                           "rel_l2_err_per_field": [float(v) for v in rel],
+                           "rel_l2_err_all": float(math.sqrt(num.sum() / max(den.sum(), 1e-300))),
+                           "rel_l2_err_without_closure": 1.0}
+        log("a-priori (held-out): relative L2 error per field %s, all %.4f (1 without closure)" % (
+            np.array2string(rel, precision=4), out["a_priori"]["rel_l2_err_all"]))
 
     # ---- a-posteriori: coarse runs with and without the closure ----
     steps_c = int(round(args.t_end / dt_c))
