@@ -40,7 +40,8 @@ class _Grid(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int * 3), ("h", ctypes.c_double * 3), ("r", ctypes.c_int),
                 ("a", ctypes.c_double * _MAXR), ("c0", ctypes.c_double),
                 ("c", ctypes.c_double * _MAXR), ("Re", ctypes.c_double),
-                ("Mach", ctypes.c_double), ("Pr", ctypes.c_double), ("gamma", ctypes.c_double)]
+                ("Mach", ctypes.c_double), ("Pr", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("sym", ctypes.c_int * 3)]
 
 
 RHS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
@@ -55,8 +56,8 @@ def lib():
         _lib = ctypes.CDLL(build())
         dp = ctypes.POINTER(ctypes.c_double)
         gp = ctypes.POINTER(_Grid)
-        _lib.ora_d1.argtypes = [gp, dp, ctypes.c_int, dp]
-        _lib.ora_d2.argtypes = [gp, dp, ctypes.c_int, dp]
+        _lib.ora_d1.argtypes = [gp, dp, ctypes.c_int, ctypes.c_int, dp]
+        _lib.ora_d2.argtypes = [gp, dp, ctypes.c_int, ctypes.c_int, dp]
         _lib.ora_rhs.argtypes = [gp, dp, dp]
         _lib.ora_rk3_step.argtypes = [gp, dp, dp, ctypes.c_double, ctypes.c_int]
         _lib.ora_rk3_generic.argtypes = [ctypes.c_long, dp, dp, ctypes.c_double, ctypes.c_int,
@@ -79,6 +80,7 @@ class Params:
     Pr: float = 0.71
     gamma: float = 1.4
     spacing: tuple = field(default=None)  # overrides length/n when given (patch evaluation)
+    bc: tuple = (0, 0, 0)              # per axis: 0 periodic, 1 symmetry boundaries
 
     def h(self):
         if self.spacing is not None:
@@ -103,6 +105,10 @@ def _grid(p: Params):
         g.c[m] = float(c[m])
     g.c0 = float(c0)
     g.Re, g.Mach, g.Pr, g.gamma = float(p.Re), float(p.Mach), float(p.Pr), float(p.gamma)
+    for i in range(3):
+        if p.bc[i] not in (0, 1):
+            raise ValueError("bc must be 0 (periodic) or 1 (symmetry) per axis")
+        g.sym[i] = int(p.bc[i])
     return g
 
 
@@ -118,21 +124,22 @@ def _state(q, p):
     return q
 
 
-def d1(f, axis, p: Params):
-    """Order-p central first derivative of a (nz, ny, nx) array along axis 0=x, 1=y, 2=z."""
+def d1(f, axis, p: Params, parity=1):
+    """Order-p central first derivative of a (nz, ny, nx) array along axis 0=x, 1=y, 2=z.
+    parity (+1 / -1): how f continues beyond a symmetry boundary on that axis."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.empty_like(f)
     g = _grid(p)
-    lib().ora_d1(ctypes.byref(g), _dp(f), int(axis), _dp(out))
+    lib().ora_d1(ctypes.byref(g), _dp(f), int(axis), int(parity), _dp(out))
     return out
 
 
-def d2(f, axis, p: Params):
-    """Order-p central second derivative along axis 0=x, 1=y, 2=z."""
+def d2(f, axis, p: Params, parity=1):
+    """Order-p central second derivative along axis 0=x, 1=y, 2=z (parity as in d1)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.empty_like(f)
     g = _grid(p)
-    lib().ora_d2(ctypes.byref(g), _dp(f), int(axis), _dp(out))
+    lib().ora_d2(ctypes.byref(g), _dp(f), int(axis), int(parity), _dp(out))
     return out
 
 
@@ -201,6 +208,8 @@ def rk3_at_points(q, p: Params, dt, points, nsteps=1):
     as on the full grid: the wrapped edges of the copy never reach the centre.
     Returns an array (len(points), 5).
     """
+    if any(p.bc):
+        raise ValueError("patch evaluation assumes periodic axes")
     q = _state(q, p)
     nx, ny, nz = p.n
     r = p.order // 2
@@ -221,6 +230,8 @@ def rk3_at_points(q, p: Params, dt, points, nsteps=1):
 
 def rhs_at_points(q, p: Params, points):
     """One-by-one oracle residual at the given (x, y, z) points (patch of half-width 2r)."""
+    if any(p.bc):
+        raise ValueError("patch evaluation assumes periodic axes")
     q = _state(q, p)
     nx, ny, nz = p.n
     r = p.order // 2

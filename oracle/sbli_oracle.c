@@ -12,8 +12,9 @@
  * Everything is written as whole-array loops in the order the paper states the
  * method, in double precision, built with -O2 -ffp-contract=off.  No blocking,
  * fusion or reordering beyond the definitions:
- *   - grid x_i = i*dx on a periodic box, indices wrap mod N (Sec. "Grid",
- *     Sec. "Boundary conditions": periodic halo exchange);
+ *   - grid x_i = i*dx; per axis either periodic (indices wrap mod N) or with
+ *     symmetry boundaries (mirror images beyond each end, vector components
+ *     normal to the boundary negated) (Sec. "Grid", Sec. "Boundary conditions");
  *   - central first / second derivative of order p = 2r (Sec. "Discretisation
  *     schemes"), the Laplacian of the viscous term by the second-derivative
  *     stencil (Sec. "3D Taylor-Green vortex", after the skew-symmetric equation);
@@ -52,6 +53,7 @@ typedef struct {
     double c0;             /* second-derivative centre weight                */
     double c[ORA_MAXR];    /* second-derivative weights c_1..c_r             */
     double Re, Mach, Pr, gamma;
+    int sym[3];            /* per axis: 0 periodic, 1 symmetry boundaries     */
 } ora_grid;
 
 static long npts(const ora_grid* g) { return (long)g->n[0] * g->n[1] * g->n[2]; }
@@ -66,17 +68,32 @@ static double* alloc_arr(long n) {
     return p;
 }
 
-/* Value of array f at (i,j,k) shifted by m along `axis`, periodic. */
-static double at_shift(const ora_grid* g, const double* f, int i, int j, int k, int axis, int m) {
-    int ii = i, jj = j, kk = k;
-    if (axis == 0) ii = wrapi(i + m, g->n[0]);
-    else if (axis == 1) jj = wrapi(j + m, g->n[1]);
-    else kk = wrapi(k + m, g->n[2]);
-    return f[((long)kk * g->n[1] + jj) * g->n[0] + ii];
+/*
+ * Value of array f at (i,j,k) shifted by m along `axis` (|m| < n).  Periodic
+ * axes wrap.  On a symmetry axis (Sec. "Boundary conditions") the points beyond
+ * each end mirror the points inside, the last point mirroring to the first halo
+ * point (f at index N is f at N-1, at N+1 is f at N-2; at -1 is f at 0, at -2 is
+ * f at 1); a field that is a vector component in that direction (or any field
+ * odd under the mirror, par = -1) changes sign there.
+ */
+static double at_shift(const ora_grid* g, const double* f, int i, int j, int k, int axis, int m, int par) {
+    int idx[3] = {i, j, k};
+    int v = idx[axis] + m;
+    const int n = g->n[axis];
+    double sign = 1.0;
+    if (g->sym[axis]) {
+        if (v < 0) { v = -1 - v; sign = par; }
+        else if (v >= n) { v = 2 * n - 1 - v; sign = par; }
+    } else {
+        v = wrapi(v, n);
+    }
+    idx[axis] = v;
+    return sign * f[((long)idx[2] * g->n[1] + idx[1]) * g->n[0] + idx[0]];
 }
 
-/* First derivative along `axis`: D f_i = sum_m a_m (f_{i+m} - f_{i-m}) / h. */
-void ora_d1(const ora_grid* g, const double* f, int axis, double* out) {
+/* First derivative along `axis`: D f_i = sum_m a_m (f_{i+m} - f_{i-m}) / h.
+ * par: parity of f under the mirror of a symmetry boundary on `axis`. */
+void ora_d1(const ora_grid* g, const double* f, int axis, int par, double* out) {
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
 #pragma omp parallel for schedule(static)
     for (int k = 0; k < nz; ++k)
@@ -84,8 +101,8 @@ void ora_d1(const ora_grid* g, const double* f, int axis, double* out) {
             for (int i = 0; i < nx; ++i) {
                 double s = 0.0;
                 for (int m = 1; m <= g->r; ++m) {
-                    double fp = at_shift(g, f, i, j, k, axis, m);
-                    double fm = at_shift(g, f, i, j, k, axis, -m);
+                    double fp = at_shift(g, f, i, j, k, axis, m, par);
+                    double fm = at_shift(g, f, i, j, k, axis, -m, par);
                     s += g->a[m - 1] * (fp - fm);
                 }
                 out[((long)k * ny + j) * nx + i] = s / g->h[axis];
@@ -93,8 +110,8 @@ void ora_d1(const ora_grid* g, const double* f, int axis, double* out) {
 }
 
 /* Second derivative along `axis`:
- * D2 f_i = [c0 f_i + sum_m c_m (f_{i+m} + f_{i-m})] / h^2. */
-void ora_d2(const ora_grid* g, const double* f, int axis, double* out) {
+ * D2 f_i = [c0 f_i + sum_m c_m (f_{i+m} + f_{i-m})] / h^2.  par as in ora_d1. */
+void ora_d2(const ora_grid* g, const double* f, int axis, int par, double* out) {
     const int nx = g->n[0], ny = g->n[1], nz = g->n[2];
     const double h2 = g->h[axis] * g->h[axis];
 #pragma omp parallel for schedule(static)
@@ -104,8 +121,8 @@ void ora_d2(const ora_grid* g, const double* f, int axis, double* out) {
                 long id = ((long)k * ny + j) * nx + i;
                 double s = g->c0 * f[id];
                 for (int m = 1; m <= g->r; ++m) {
-                    double fp = at_shift(g, f, i, j, k, axis, m);
-                    double fm = at_shift(g, f, i, j, k, axis, -m);
+                    double fp = at_shift(g, f, i, j, k, axis, m, par);
+                    double fm = at_shift(g, f, i, j, k, axis, -m, par);
                     s += g->c[m - 1] * (fp + fm);
                 }
                 out[id] = s / h2;
@@ -138,6 +155,17 @@ static void axpy_prod(long n, double alpha, const double* x, const double* y, do
  *   R_E    = -1/2 sum_j [D_j(rho E u_j) + u_j D_j(rho E) + rho E g_jj]
  *            - sum_j D_j(p u_j) + kappa sum_j D2_j T + sum_j D_j(sum_i u_i tau_ij)
  */
+/*
+ * Parity under the mirror of a symmetry boundary on axis a of the velocity (or
+ * momentum) component i: odd for the component normal to the boundary, even
+ * otherwise.  Density, energy, pressure and temperature are even; a product's
+ * parity is the product of its factors' parities; the viscous-work flux
+ * V_j = u_i tau_ij is odd under the mirror on axis j (tau_ij has the parity of
+ * u_i u_j).  With these, a derivative on a symmetry axis sees exactly the
+ * mirror image of the field beyond the boundary.
+ */
+#define SGN(i, a) ((i) == (a) ? -1 : 1)
+
 void ora_rhs(const ora_grid* g, const double* q, double* R) {
     const long P = npts(g);
     const double gam = g->gamma, M2 = g->Mach * g->Mach;
@@ -173,7 +201,7 @@ void ora_rhs(const ora_grid* g, const double* q, double* R) {
     }
     /* velocity gradient g_ij = D_j u_i (inner derivatives of the nested terms) */
     for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) ora_d1(g, u[i], j, gr[i][j]);
+        for (int j = 0; j < 3; ++j) ora_d1(g, u[i], j, SGN(i, j), gr[i][j]);
 #pragma omp parallel for schedule(static)
     for (long n = 0; n < P; ++n) theta[n] = gr[0][0][n] + gr[1][1][n] + gr[2][2][n];
     /* viscous work flux V_j = sum_i u_i tau_ij */
@@ -193,8 +221,8 @@ void ora_rhs(const ora_grid* g, const double* q, double* R) {
 
     /* ---- continuity ---- */
     for (int j = 0; j < 3; ++j) {
-        ora_d1(g, m[j], j, t1);            /* D_j(rho u_j)   */
-        ora_d1(g, rho, j, t2);             /* D_j rho        */
+        ora_d1(g, m[j], j, -1, t1);        /* D_j(rho u_j)   */
+        ora_d1(g, rho, j, 1, t2);          /* D_j rho        */
         axpy_prod(P, -0.5, t1, NULL, R_rho);
         axpy_prod(P, -0.5, u[j], t2, R_rho);
         axpy_prod(P, -0.5, rho, gr[j][j], R_rho);
@@ -205,23 +233,23 @@ void ora_rhs(const ora_grid* g, const double* q, double* R) {
         for (int j = 0; j < 3; ++j) {
 #pragma omp parallel for schedule(static)
             for (long n = 0; n < P; ++n) t3[n] = m[i][n] * u[j][n];   /* rho u_i u_j */
-            ora_d1(g, t3, j, t1);                                        /* D_j(rho u_i u_j) */
-            ora_d1(g, m[i], j, t2);                                      /* D_j(rho u_i)     */
+            ora_d1(g, t3, j, -SGN(i, j), t1);                            /* D_j(rho u_i u_j) */
+            ora_d1(g, m[i], j, SGN(i, j), t2);                           /* D_j(rho u_i)     */
             axpy_prod(P, -0.5, t1, NULL, R_m[i]);
             axpy_prod(P, -0.5, u[j], t2, R_m[i]);
             axpy_prod(P, -0.5, m[i], gr[j][j], R_m[i]);
         }
-        ora_d1(g, p, i, t1);                                             /* D_i p */
+        ora_d1(g, p, i, 1, t1);                                          /* D_i p */
         axpy_prod(P, -1.0, t1, NULL, R_m[i]);
         /* (1/Re) [ sum_j D2_j u_i + 1/3 D2_i u_i + 1/3 sum_{k != i} D_i(g_kk) ] */
         for (int j = 0; j < 3; ++j) {
-            ora_d2(g, u[i], j, t1);
+            ora_d2(g, u[i], j, SGN(i, j), t1);
             axpy_prod(P, inv_Re, t1, NULL, R_m[i]);
             if (j == i) axpy_prod(P, inv_Re / 3.0, t1, NULL, R_m[i]);
         }
         for (int k = 0; k < 3; ++k) {
             if (k == i) continue;
-            ora_d1(g, gr[k][k], i, t1);                                  /* D_i(D_k u_k) */
+            ora_d1(g, gr[k][k], i, 1, t1);                               /* D_i(D_k u_k) */
             axpy_prod(P, inv_Re / 3.0, t1, NULL, R_m[i]);
         }
     }
@@ -230,18 +258,18 @@ void ora_rhs(const ora_grid* g, const double* q, double* R) {
     for (int j = 0; j < 3; ++j) {
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < P; ++n) t3[n] = rE[n] * u[j][n];           /* rho E u_j */
-        ora_d1(g, t3, j, t1);
-        ora_d1(g, rE, j, t2);
+        ora_d1(g, t3, j, -1, t1);
+        ora_d1(g, rE, j, 1, t2);
         axpy_prod(P, -0.5, t1, NULL, R_E);
         axpy_prod(P, -0.5, u[j], t2, R_E);
         axpy_prod(P, -0.5, rE, gr[j][j], R_E);
 #pragma omp parallel for schedule(static)
         for (long n = 0; n < P; ++n) t3[n] = p[n] * u[j][n];            /* p u_j */
-        ora_d1(g, t3, j, t1);
+        ora_d1(g, t3, j, -1, t1);
         axpy_prod(P, -1.0, t1, NULL, R_E);
-        ora_d2(g, T, j, t1);                                            /* D2_j T */
+        ora_d2(g, T, j, 1, t1);                                         /* D2_j T */
         axpy_prod(P, kappa, t1, NULL, R_E);
-        ora_d1(g, V[j], j, t1);                                         /* D_j(u_i tau_ij) */
+        ora_d1(g, V[j], j, -1, t1);                                     /* D_j(u_i tau_ij) */
         axpy_prod(P, 1.0, t1, NULL, R_E);
     }
 
@@ -350,12 +378,12 @@ void ora_diagnostics(const ora_grid* g, const double* q, double out[7], long fla
     }
     double *dwdy = alloc_arr(P), *dvdz = alloc_arr(P), *dudz = alloc_arr(P);
     double *dwdx = alloc_arr(P), *dvdx = alloc_arr(P), *dudy = alloc_arr(P);
-    ora_d1(g, u[2], 1, dwdy);
-    ora_d1(g, u[1], 2, dvdz);
-    ora_d1(g, u[0], 2, dudz);
-    ora_d1(g, u[2], 0, dwdx);
-    ora_d1(g, u[1], 0, dvdx);
-    ora_d1(g, u[0], 1, dudy);
+    ora_d1(g, u[2], 1, 1, dwdy);
+    ora_d1(g, u[1], 2, 1, dvdz);
+    ora_d1(g, u[0], 2, 1, dudz);
+    ora_d1(g, u[2], 0, 1, dwdx);
+    ora_d1(g, u[1], 0, 1, dvdx);
+    ora_d1(g, u[0], 1, 1, dudy);
     neum acc[7];
     memset(acc, 0, sizeof(acc));
     long nonfinite = 0, badrho = 0, badp = 0;
