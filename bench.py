@@ -133,6 +133,52 @@ def measure_batch(sbli, torch, steps):
             "unit": "Mpoint-RK3-steps/s", "variant": v, "zmax": zmax, "status": code}
 
 
+def measure_closure(torch, n=64, batch=4, reps=10):
+    """The learned closure's BF16-MFMA kernels at the coarse grid: forward + backward
+    (data and weight gradients) of a batch, and the forward of one sample."""
+    import numpy as np
+    import synth
+    from paper_1609_01277_amd import closure
+    net = closure.ClosureNet(n, batch)
+    net.set_params(synth.closure_init_params(1609))
+    st = np.zeros(closure.N_STATS, dtype=np.float32)
+    st[5:10] = 1.0
+    st[15:20] = 1.0
+    st[20:25] = 1e30
+    net.set_stats(st)
+    g = torch.Generator(device="cuda").manual_seed(1609)
+    x = torch.randn((batch, 5, n, n, n), device="cuda", generator=g)
+    y = torch.randn((batch, 5, n, n, n), device="cuda", generator=g)
+    net.gradients(x, y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        net.gradients(x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / reps
+    out = torch.empty((1, 5, n, n, n), device="cuda")
+    net.forward(x[:1], out)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        net.forward(x[:1], out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / reps
+    net.close()
+    # padded MFMA work: channels 8 -> 32 -> 32 -> 32 (5 padded), 27 taps, 2 flops per MAC;
+    # forward once, backward twice (data and weight gradients)
+    macs = n ** 3 * 27 * (8 * 32 + 32 * 32 + 32 * 32)
+    tf_train = 3 * 2 * macs * batch / (ms_train * 1e-3) / 1e12
+    tf_fwd = 2 * macs / (ms_fwd * 1e-3) / 1e12
+    return {"grid": n, "batch": batch, "fwd_bwd_ms": ms_train, "fwd_bwd_padded_tflops": tf_train,
+            "forward_ms_1_sample": ms_fwd, "forward_padded_tflops": tf_fwd,
+            "bf16_dense_peak_tflops": 2500.0, "frac_fwd_bwd": tf_train / 2500.0}
+
+
 def cpu_baseline(n=256, order=4):
     """The FP64 oracle, as it stands, on the host cores: one RK3 step of TGV n^3."""
     import oracle
@@ -159,6 +205,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and order-8 lines")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=256)
+    ap.add_argument("--closure-only", action="store_true",
+                    help="only time the learned closure's kernels (64^3, batch 4) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -191,6 +239,9 @@ def main():
         __graft_entry__.build()
     import paper_1609_01277_amd as sbli
 
+    if args.closure_only:
+        print(json.dumps(measure_closure(torch)), flush=True)
+        return
     log("main: TGV %d^3 %s order %d, %d steps after %d warm-up" % (args.n, args.dtype, args.order,
                                                                   args.steps, args.warmup))
     main_r = measure(sbli, torch, args.n, args.order, args.dtype, args.steps, args.warmup)
@@ -213,6 +264,12 @@ def main():
         extra["batched_f32_order4_64boxes"] = rb
         log("extra batched: graph %.1f vs sequential %.1f Mpt-steps/s (x%.2f)" % (
             rb["graph_value"], rb["sequential_value"], rb["speedup"]))
+
+    if not args.no_extra:
+        rc = measure_closure(torch)
+        extra["closure_bf16_64cube"] = rc
+        log("extra closure: fwd+bwd batch 4 %.2f ms (%.1f padded TFLOP/s), forward %.2f ms" % (
+            rc["fwd_bwd_ms"], rc["fwd_bwd_padded_tflops"], rc["forward_ms_1_sample"]))
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -18,8 +18,8 @@
  *  - Streams: all device work is enqueued on the hipStream_t given at init
  *    (pass NULL for the default stream).  Calls return without waiting unless
  *    stated otherwise.
- *  - Grid: x_i = i*lx/nx (same in y, z) on a periodic box; the domain is
- *    [0, lx) x [0, ly) x [0, lz) and the reference length L = 1.
+ *  - Grid: x_i = i*lx/nx (same in y, z); each axis periodic or with symmetry
+ *    boundaries (sbli_params.bc); the reference length L = 1.
  */
 #ifndef SBLI_H
 #define SBLI_H
@@ -54,7 +54,16 @@ typedef struct sbli_params {
     double Re, Mach, Pr, gamma;
     int order;
     int dtype;
+    /* Boundary condition per axis (x, y, z), Sec. "Boundary conditions":
+     * SBLI_BC_PERIODIC (0), or SBLI_BC_SYMMETRY (1): beyond each end the
+     * fields are the mirror image of the points inside (point N is point N-1,
+     * N+1 is N-2, -1 is 0, ...), the momentum component normal to the
+     * boundary with opposite sign.  The points sit at x_i = i * lx / nx. */
+    int bc[3];
 } sbli_params;
+
+#define SBLI_BC_PERIODIC 0
+#define SBLI_BC_SYMMETRY 1
 
 typedef struct sbli_ctx sbli_ctx;
 
@@ -93,8 +102,11 @@ int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase);
  * momentum, energy; stress tensor; heat flux; eq. eos; total energy) with the
  * skew-symmetric convective form (eq. skew_symmetric_formulation), the viscous
  * Laplacian by the second-derivative stencil, nested derivatives inner-first,
- * periodic in every direction.  `q` and `rhs` are device states of the context's
- * dtype and must not overlap.
+ * with the boundary condition of each axis (sbli_params.bc; on a symmetry axis
+ * every stencil, the nested ones included, sees the mirror image of the state,
+ * which makes the result that of the periodic box of twice the length holding
+ * the state and its mirror image).  `q` and `rhs` are device states of the
+ * context's dtype and must not overlap.
  */
 int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs);
 
@@ -133,7 +145,8 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *
  * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
  * sbli_variant_info: info = {tile x, tile y, load-ahead depth, register-window
- *   rotation (1) or shifting (0)} of a variant.
+ *   rotation (1) or shifting (0), wavefronts per SIMD its register allocation
+ *   allows at least (1: as many registers as the kernel wants)} of a variant.
  * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
  *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).  sbli_set_tuning waits
  *   for the context's stream (it updates a small device table).
@@ -144,7 +157,7 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *   unspecified (they are advanced in time).  Synchronises the stream.
  */
 int sbli_num_variants(const sbli_ctx* ctx);
-int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[4]);
+int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[5]);
 int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk);
 int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk);
 int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms);

@@ -22,30 +22,39 @@ __all__ = ["Solver", "make_params", "SbliError", "sbli_init", "sbli_destroy", "s
 DIAG_NAMES = ("Ek", "enstrophy", "rho", "rhou", "rhov", "rhow", "rhoE")
 
 
-def make_params(n, order=4, dtype="f64", Re=1600.0, Mach=0.1, Pr=0.71, gamma=1.4, length=None):
-    """sbli_params for an n = (nx, ny, nz) (or int) periodic box of side 2*pi (default)."""
+_BC = {"periodic": _lib.SBLI_BC_PERIODIC, "symmetry": _lib.SBLI_BC_SYMMETRY,
+       0: _lib.SBLI_BC_PERIODIC, 1: _lib.SBLI_BC_SYMMETRY}
+
+
+def make_params(n, order=4, dtype="f64", Re=1600.0, Mach=0.1, Pr=0.71, gamma=1.4, length=None,
+                bc=("periodic", "periodic", "periodic")):
+    """sbli_params for an n = (nx, ny, nz) (or int) box of side 2*pi (default); bc per
+    axis "periodic" or "symmetry" (0 / 1)."""
     if isinstance(n, int):
         n = (n, n, n)
     if length is None:
         length = (2 * math.pi,) * 3
     dt = {"f64": SBLI_F64, "f32": SBLI_F32}[dtype]
-    return sbli_params(int(n[0]), int(n[1]), int(n[2]), float(length[0]), float(length[1]),
-                       float(length[2]), float(Re), float(Mach), float(Pr), float(gamma), int(order),
-                       dt)
+    p = sbli_params(int(n[0]), int(n[1]), int(n[2]), float(length[0]), float(length[1]),
+                    float(length[2]), float(Re), float(Mach), float(Pr), float(gamma), int(order), dt)
+    for d in range(3):
+        p.bc[d] = _BC[bc[d]]
+    return p
 
 
 class Solver:
-    """One periodic box on the current HIP device and stream.
+    """One box (periodic or with symmetry boundaries per axis) on the current HIP device
+    and stream.
 
     State tensors are torch tensors of shape (5, nz, ny, nx), dtype float64 or
     float32, on the GPU, contiguous.
     """
 
     def __init__(self, n, order=4, dtype="f64", Re=1600.0, Mach=0.1, Pr=0.71, gamma=1.4,
-                 length=None, stream=None):
+                 length=None, stream=None, bc=("periodic", "periodic", "periodic")):
         import torch
         self.torch = torch
-        self.params = make_params(n, order, dtype, Re, Mach, Pr, gamma, length)
+        self.params = make_params(n, order, dtype, Re, Mach, Pr, gamma, length, bc)
         self.shape = (5, self.params.nz, self.params.ny, self.params.nx)
         self.dtype = torch.float64 if dtype == "f64" else torch.float32
         if stream is None:

@@ -31,7 +31,11 @@ class sbli_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
                 ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
                 ("Re", ctypes.c_double), ("Mach", ctypes.c_double), ("Pr", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("order", ctypes.c_int), ("dtype", ctypes.c_int)]
+                ("gamma", ctypes.c_double), ("order", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("bc", ctypes.c_int * 3)]
+
+SBLI_BC_PERIODIC = 0
+SBLI_BC_SYMMETRY = 1
 
 
 _lib = None
@@ -134,7 +138,7 @@ def sbli_num_variants(ctx):
 
 
 def sbli_variant_info(ctx, variant):
-    info = (ctypes.c_int * 4)()
+    info = (ctypes.c_int * 5)()
     _check(load().sbli_variant_info(ctx, int(variant), info), ctx)
     return tuple(info)
 

@@ -11,6 +11,10 @@ SOURCES = ["sbli.hip", "closure.hip", "scalar.hip"] + ["stage_%s_r%d.hip" % (t, 
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # a*b + c is fused only within one source expression (the hot arithmetic
+    # spells its fused multiply-adds out), so rounding never depends on how the
+    # compiler schedules a particular kernel variant
+    "-ffp-contract=on",
     # packed FP32 instructions stay disabled for every kernel of this library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -190,12 +190,17 @@ def main(argv=None):
                 cl.attach(s, net)
             qt, dq = s.empty_state(), s.empty_state()
             ek, en = [], []
+            ratio = []          # per diagnostic step: per-field max |C| / guard limit
+            limit = torch.tensor(st[20:25], dtype=torch.float32, device="cuda")
             t2 = time.time()
             for step in range(steps_c + 1):
                 if step % args.diag_every == 0:
                     d, code = s.diagnostics(q, check=False)
                     ek.append(d["Ek"])
                     en.append(d["enstrophy"])
+                    if mode == "closure":
+                        net.forward(q[None], pred)
+                        ratio.append((pred[0].abs().reshape(5, -1).amax(dim=1) / limit).cpu().tolist())
                 if step < steps_c:
                     s.rk3_step(q, qt, dq, dt_c, 1)
             torch.cuda.synchronize()
@@ -208,6 +213,13 @@ def main(argv=None):
                      "seconds": time.time() - t2, "Ek": ek, "enstrophy": en}
             if mode == "closure":
                 entry["guard_accepted_rejected"] = list(cl.counts(s))
+                r_ = np.array(ratio)
+                entry["guard_ratio_max_per_field"] = r_.max(axis=0).tolist()
+                over = np.nonzero(r_.max(axis=1) > 1.0)[0]
+                entry["guard_first_exceed_t"] = float(over[0] * args.diag_every * dt_c) if len(over) else None
+                log("Re %g closure: guard accepted %d rejected %d; max |C|/limit per field %s; first exceeded at t = %s" % (
+                    Re, entry["guard_accepted_rejected"][0], entry["guard_accepted_rejected"][1],
+                    np.array2string(r_.max(axis=0), precision=3), entry["guard_first_exceed_t"]))
                 cl.attach(s, None)
             res_run[mode] = entry
             log("Re %g %s: Ek err max %.4f rms %.4f; enstrophy err max %.4f rms %.4f" % (

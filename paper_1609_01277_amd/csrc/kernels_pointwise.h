@@ -94,6 +94,7 @@ __device__ __forceinline__ void block_reduce_diag(CSum (&acc)[kDiagQ], unsigned 
 template <typename T, int R>
 __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const T* __restrict__ q, int nx, int ny, int nz,
                                                                     const double* __restrict__ da, double gm1,
+                                                                    int symx, int symy, int symz,
                                                                     double* __restrict__ part) {
     const int64_t P = (int64_t)nx * ny * nz;
     const int64_t sy = nx, sz = (int64_t)nx * ny;
@@ -110,26 +111,28 @@ __global__ void __launch_bounds__(kDiagThreads) diag_partial_kernel(const T* __r
         const double m0 = (double)q[P + id], m1 = (double)q[2 * P + id], m2 = (double)q[3 * P + id];
         const double rE = (double)q[4 * P + id];
         const double u0 = m0 / rho, u1 = m1 / rho, u2 = m2 / rho;
-        // derivatives of u_b along axis a: dudy, dudz, dvdx, dvdz, dwdx, dwdy
+        // derivatives of u_b along axis a: dudy, dudz, dvdx, dvdz, dwdx, dwdy.  Each
+        // component is differentiated across the axes it is tangential to, so on
+        // a symmetry axis its mirror image has the same sign.
         double dvdx = 0, dwdx = 0, dudy = 0, dwdy = 0, dudz = 0, dvdz = 0;
 #pragma unroll
         for (int m = 1; m <= R; ++m) {
             {
-                const int64_t ip = shifted(id, i, m, nx, 1), im = shifted(id, i, -m, nx, 1);
+                const int64_t ip = shifted(id, i, m, nx, 1, symx), im = shifted(id, i, -m, nx, 1, symx);
                 const double rp = (double)q[ip], rm = (double)q[im];
                 const double w = da[0 * kMaxR + m - 1];
                 dvdx += w * ((double)q[2 * P + ip] / rp - (double)q[2 * P + im] / rm);
                 dwdx += w * ((double)q[3 * P + ip] / rp - (double)q[3 * P + im] / rm);
             }
             {
-                const int64_t ip = shifted(id, j, m, ny, sy), im = shifted(id, j, -m, ny, sy);
+                const int64_t ip = shifted(id, j, m, ny, sy, symy), im = shifted(id, j, -m, ny, sy, symy);
                 const double rp = (double)q[ip], rm = (double)q[im];
                 const double w = da[1 * kMaxR + m - 1];
                 dudy += w * ((double)q[P + ip] / rp - (double)q[P + im] / rm);
                 dwdy += w * ((double)q[3 * P + ip] / rp - (double)q[3 * P + im] / rm);
             }
             {
-                const int64_t ip = shifted(id, k, m, nz, sz), im = shifted(id, k, -m, nz, sz);
+                const int64_t ip = shifted(id, k, m, nz, sz, symz), im = shifted(id, k, -m, nz, sz, symz);
                 const double rp = (double)q[ip], rm = (double)q[im];
                 const double w = da[2 * kMaxR + m - 1];
                 dudz += w * ((double)q[P + ip] / rp - (double)q[P + im] / rm);

@@ -20,8 +20,9 @@
 // Columns of the R-ring around the tile are handled by extra "halo" threads
 // (whole wavefronts apart from the interior ones); the 2R-ring of u needed only
 // for the x/y gradient stencils of halo columns is loaded directly.  Periodic
-// wrap is folded into the column coordinates, so ragged tiles need no special
-// case beyond masking their stores.
+// wrap (or, on a symmetry axis, the mirror image with the normal momentum
+// negated) is folded into the column and plane coordinates, so ragged tiles and
+// boundaries need no special case beyond masking the stores.
 #pragma once
 
 #include <type_traits>
@@ -67,6 +68,12 @@ __device__ __forceinline__ float fast_recip(float x) {
     return __builtin_fmaf(r, e, r);
 }
 
+// a*b + c with one rounding.  The residual arithmetic spells out its fused
+// multiply-adds (the library is built with contraction limited to single
+// expressions), so every launch variant rounds every point identically.
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 template <typename T>
 __device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T gM2) {
     PF<T> s;
@@ -79,7 +86,8 @@ __device__ __forceinline__ PF<T> make_pf(T rho, T m0, T m1, T m2, T E, T gm1, T 
     s.u0 = m0 * rr;
     s.u1 = m1 * rr;
     s.u2 = m2 * rr;
-    s.p = gm1 * (E - T(0.5) * (m0 * s.u0 + m1 * s.u1 + m2 * s.u2));
+    const T ke2 = fmaT(m2, s.u2, fmaT(m1, s.u1, m0 * s.u0));    // 2 x kinetic energy
+    s.p = gm1 * fmaT(T(-0.5), ke2, E);
     s.Tm = gM2 * s.p * rr;
     return s;
 }
@@ -116,27 +124,29 @@ struct DirSums {
     __device__ __forceinline__ void add(const PF<T>& a, T Va, T Tha, const PF<T>& b, T Vb, T Thb, T w, T w2) {
         const T ua = d == 0 ? a.u0 : (d == 1 ? a.u1 : a.u2);
         const T ub = d == 0 ? b.u0 : (d == 1 ? b.u1 : b.u2);
-        dRho += w * (a.rho - b.rho);
-        dM0 += w * (a.m0 - b.m0);
-        dM1 += w * (a.m1 - b.m1);
-        dM2 += w * (a.m2 - b.m2);
-        T fa0 = a.m0 * ua, fb0 = b.m0 * ub;
-        T fa1 = a.m1 * ua, fb1 = b.m1 * ub;
-        T fa2 = a.m2 * ua, fb2 = b.m2 * ub;
-        if (d == 0) { fa0 += T(2) * a.p; fb0 += T(2) * b.p; }
-        if (d == 1) { fa1 += T(2) * a.p; fb1 += T(2) * b.p; }
-        if (d == 2) { fa2 += T(2) * a.p; fb2 += T(2) * b.p; }
-        dF0 += w * (fa0 - fb0);
-        dF1 += w * (fa1 - fb1);
-        dF2 += w * (fa2 - fb2);
-        dE += w * (a.E - b.E);
-        dH += w * (((a.E + T(2) * a.p) * ua - T(2) * Va) - ((b.E + T(2) * b.p) * ub - T(2) * Vb));
-        dU += w * (ua - ub);
-        dTh += w * (Tha - Thb);
-        d2U0 += w2 * (a.u0 + b.u0);
-        d2U1 += w2 * (a.u1 + b.u1);
-        d2U2 += w2 * (a.u2 + b.u2);
-        d2T += w2 * (a.Tm + b.Tm);
+        dRho = fmaT(w, a.rho - b.rho, dRho);
+        dM0 = fmaT(w, a.m0 - b.m0, dM0);
+        dM1 = fmaT(w, a.m1 - b.m1, dM1);
+        dM2 = fmaT(w, a.m2 - b.m2, dM2);
+        // momentum fluxes rho u_i u_d (+ 2p for i = d): differences a - b
+        const T pa2 = T(2) * (a.p - b.p);
+        const T f0 = d == 0 ? fmaT(a.m0, ua, pa2 - b.m0 * ub) : fmaT(a.m0, ua, -(b.m0 * ub));
+        const T f1 = d == 1 ? fmaT(a.m1, ua, pa2 - b.m1 * ub) : fmaT(a.m1, ua, -(b.m1 * ub));
+        const T f2 = d == 2 ? fmaT(a.m2, ua, pa2 - b.m2 * ub) : fmaT(a.m2, ua, -(b.m2 * ub));
+        dF0 = fmaT(w, f0, dF0);
+        dF1 = fmaT(w, f1, dF1);
+        dF2 = fmaT(w, f2, dF2);
+        dE = fmaT(w, a.E - b.E, dE);
+        // energy flux (rho E + 2p) u_d - 2 V_d: difference a - b
+        const T hb = fmaT(fmaT(T(2), b.p, b.E), ub, T(-2) * Vb);
+        const T fh = fmaT(fmaT(T(2), a.p, a.E), ua, fmaT(T(-2), Va, -hb));
+        dH = fmaT(w, fh, dH);
+        dU = fmaT(w, ua - ub, dU);
+        dTh = fmaT(w, Tha - Thb, dTh);
+        d2U0 = fmaT(w2, a.u0 + b.u0, d2U0);
+        d2U1 = fmaT(w2, a.u1 + b.u1, d2U1);
+        d2U2 = fmaT(w2, a.u2 + b.u2, d2U2);
+        d2T = fmaT(w2, a.Tm + b.Tm, d2T);
     }
     // Adds this direction's part of the residual (paper eq. mass, momentum,
     // energy in the skew-symmetric form, regrouped by linearity) at point s.
@@ -144,21 +154,21 @@ struct DirSums {
     __device__ __forceinline__ void finish(const PF<T>& s, T c0, const BoxConst<T>& c, T& Rr, T& R0, T& R1, T& R2,
                                            T& RE) {
         const T ud = d == 0 ? s.u0 : (d == 1 ? s.u1 : s.u2);
-        const T e0 = d2U0 + c0 * s.u0;
-        const T e1 = d2U1 + c0 * s.u1;
-        const T e2 = d2U2 + c0 * s.u2;
-        const T eT = d2T + c0 * s.Tm;
+        const T e0 = fmaT(c0, s.u0, d2U0);
+        const T e1 = fmaT(c0, s.u1, d2U1);
+        const T e2 = fmaT(c0, s.u2, d2U2);
+        const T eT = fmaT(c0, s.Tm, d2T);
         const T dMd = d == 0 ? dM0 : (d == 1 ? dM1 : dM2);
-        Rr -= T(0.5) * (dMd + ud * dRho + s.rho * dU);
-        R0 += c.inv_Re * e0 - T(0.5) * (dF0 + ud * dM0 + s.m0 * dU);
-        R1 += c.inv_Re * e1 - T(0.5) * (dF1 + ud * dM1 + s.m1 * dU);
-        R2 += c.inv_Re * e2 - T(0.5) * (dF2 + ud * dM2 + s.m2 * dU);
+        const T h = T(-0.5);
+        Rr = fmaT(h, dMd + fmaT(ud, dRho, s.rho * dU), Rr);
+        R0 = fmaT(c.inv_Re, e0, fmaT(h, dF0 + fmaT(ud, dM0, s.m0 * dU), R0));
+        R1 = fmaT(c.inv_Re, e1, fmaT(h, dF1 + fmaT(ud, dM1, s.m1 * dU), R1));
+        R2 = fmaT(c.inv_Re, e2, fmaT(h, dF2 + fmaT(ud, dM2, s.m2 * dU), R2));
         const T ed = d == 0 ? e0 : (d == 1 ? e1 : e2);
-        const T extra = c.inv_3Re * (ed + dTh);
-        if (d == 0) R0 += extra;
-        if (d == 1) R1 += extra;
-        if (d == 2) R2 += extra;
-        RE += c.kappa * eT - T(0.5) * (dH + ud * dE + s.E * dU);
+        if (d == 0) R0 = fmaT(c.inv_3Re, ed + dTh, R0);
+        if (d == 1) R1 = fmaT(c.inv_3Re, ed + dTh, R1);
+        if (d == 2) R2 = fmaT(c.inv_3Re, ed + dTh, R2);
+        RE = fmaT(c.kappa, eT, fmaT(h, dH + fmaT(ud, dE, s.E * dU), RE));
     }
 };
 
@@ -209,7 +219,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
         cx = t2 % TX;
         cy = side ? TY + k : -R + k;
     }
-    const int64_t col = (int64_t)wrap_mod(y0 + cy, ny) * nx + wrap_mod(x0 + cx, nx);
+    // Periodic axes wrap; symmetry axes mirror, and a mirrored column carries the
+    // sign-bit mask of the momentum component normal to that boundary.
+    unsigned fcx, fcy;
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fcy) * nx + fold_index(x0 + cx, nx, c.sym[0], fcx);
     const bool store = interior && (x0 + cx < nx) && (y0 + cy < ny);
 
     // u-only ring point of this thread (if any): E2 minus E1.
@@ -238,7 +251,8 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             oy = (corner & 2) ? TY + ky : -R + ky;
         }
     }
-    const int64_t ocol = (int64_t)wrap_mod(y0 + oy, ny) * nx + wrap_mod(x0 + ox, nx);
+    unsigned fox, foy;
+    const int64_t ocol = (int64_t)fold_index(y0 + oy, ny, c.sym[1], foy) * nx + fold_index(x0 + ox, nx, c.sym[0], fox);
 
     // ---- register windows ----
     constexpr int W = 3 * R + 1;
@@ -252,11 +266,16 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     // iteration it starts, and consumed one iteration later.
     T pq0 = 0, pq1 = 0, pq2 = 0, pq3 = 0, pq4 = 0;   // next q (own column)
     T pr0 = 1, pr1 = 0, pr2 = 0, pr3 = 0;            // next ring point (rho, rho u_i)
+    // Sign-bit masks of the z-momentum of the planes just requested (mirror
+    // images beyond a z symmetry boundary).  The loaded values stay untouched
+    // until they are used, so a prefetch never waits for its data.
+    unsigned pqz = 0u, prz = 0u;
+    const int symz = c.sym[2];   // planes stay within [-2R, nz + 2R): one mirror or wrap at most
     T pd0 = 0, pd1 = 0, pd2 = 0, pd3 = 0, pd4 = 0;   // next dq (own column)
     auto issue = [&](int it) {
         const int L = z0 - 2 * R + it;
         if (e1) {
-            const int64_t idx = (int64_t)wrap_mod(L, nz) * plane + col;
+            const int64_t idx = (int64_t)map_index(L, nz, symz, pqz) * plane + col;
             pq0 = q[idx];
             pq1 = q[P + idx];
             pq2 = q[2 * P + idx];
@@ -264,14 +283,14 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             pq4 = q[4 * P + idx];
         }
         if (has_out && it >= 2 * R) {
-            const int64_t idx = (int64_t)wrap_mod(L - R, nz) * plane + ocol;
+            const int64_t idx = (int64_t)map_index(L - R, nz, symz, prz) * plane + ocol;
             pr0 = q[idx];
             pr1 = q[P + idx];
             pr2 = q[2 * P + idx];
             pr3 = q[3 * P + idx];
         }
         if (PRE == 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store && it >= 4 * R) {
-            const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+            const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
             pd0 = dq[idx];
             pd1 = dq[P + idx];
             pd2 = dq[2 * P + idx];
@@ -288,8 +307,9 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
         auto slot = [](int k) { return ROT ? (k + PH) % W : k; };
             const int L = z0 - 2 * R + it;           // plane loaded this iteration
             if (PRE == 0) issue(it);
-            const T cq0 = pq0, cq1 = pq1, cq2 = pq2, cq3 = pq3, cq4 = pq4;
-            const T cr0 = pr0, cr1 = pr1, cr2 = pr2, cr3 = pr3;
+            const T cq0 = pq0, cq1 = flip_sign(pq1, fcx), cq2 = flip_sign(pq2, fcy), cq3 = flip_sign(pq3, pqz),
+                    cq4 = pq4;
+            const T cr0 = pr0, cr1 = flip_sign(pr1, fox), cr2 = flip_sign(pr2, foy), cr3 = flip_sign(pr3, prz);
             T cd[5] = {pd0, pd1, pd2, pd3, pd4};
             if (PRE > 0 && it + 1 < iters) issue(it + 1);
             // 1. plane L enters the window
@@ -326,11 +346,11 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     T sx = 0, sy = 0, sz = 0;
     #pragma unroll
                     for (int m = 1; m <= R; ++m) {
-                        sx += c.da[0][m - 1] * (s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m]);
-                        sy += c.da[1][m - 1] * (s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R]);
+                        sx = fmaT(c.da[0][m - 1], s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m], sx);
+                        sy = fmaT(c.da[1][m - 1], s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R], sy);
                         const T up = b == 0 ? Qb[slot(2 * R + m)].u0 : (b == 1 ? Qb[slot(2 * R + m)].u1 : Qb[slot(2 * R + m)].u2);
                         const T um = b == 0 ? Qb[slot(2 * R - m)].u0 : (b == 1 ? Qb[slot(2 * R - m)].u1 : Qb[slot(2 * R - m)].u2);
-                        sz += c.da[2][m - 1] * (up - um);
+                        sz = fmaT(c.da[2][m - 1], up - um, sz);
                     }
                     g[b][0] = sx;
                     g[b][1] = sy;
@@ -345,8 +365,8 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     #pragma unroll
                     for (int ii = 0; ii < 3; ++ii) {
                         T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
-                        if (ii == jj) tau -= c.inv_Re23 * theta;
-                        v += uc[ii] * tau;
+                        if (ii == jj) tau = fmaT(-c.inv_Re23, theta, tau);
+                        v = fmaT(uc[ii], tau, v);
                     }
                     V[jj] = v;
                 }
@@ -380,7 +400,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             if (do_out && interior) {
                 const int ly = cy + R, lx = cx + R;
                 if (PRE < 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store) {
-                    const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+                    const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
     #pragma unroll
                     for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
                 }
@@ -432,7 +452,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
                 }
                 if (store) {
-                    const int64_t idx = (int64_t)wrap_mod(L - 2 * R, nz) * plane + col;
+                    const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
                     T Rv[5] = {Rr, R0, R1, R2, RE};
                     if (clos != nullptr && cflag[0] != 0) {
     #pragma unroll
@@ -445,9 +465,9 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                             out[f * P + idx] = Rv[f];
                         } else {
                             T dn = dt * Rv[f];
-                            if (MODE != kModeStage1) dn += A * cd[f];
+                            if (MODE != kModeStage1) dn = fmaT(A, cd[f], dn);
                             if (MODE != kModeStage3) dq[f * P + idx] = dn;
-                            out[f * P + idx] = qv[f] + B * dn;
+                            out[f * P + idx] = fmaT(B, dn, qv[f]);
                         }
                     }
                 }
@@ -484,8 +504,10 @@ struct BoxInst {
 // by first_wg.  Workgroups are handed to the 8 XCDs round-robin by id; the id is
 // remapped so that each XCD (with its own L2) walks a contiguous run of
 // neighbouring tiles, whose halos then hit in that L2.
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT>
-__global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT))
+// MINW: the fewest wavefronts per SIMD the register allocation must allow
+// (2 caps a thread at 256 VGPRs, so two 4-wavefront workgroups share a CU).
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW>
+__global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                        const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
     const int total = gridDim.x;

@@ -81,6 +81,7 @@ static void fill_const(const sbli_ctx* x, BoxConst<T>& c) {
     c.inv_3Re = (T)(1.0 / (3.0 * x->p.Re));
     c.inv_Re23 = (T)(2.0 / (3.0 * x->p.Re));
     c.kappa = (T)(1.0 / ((g - 1.0) * M * M * x->p.Pr * x->p.Re));
+    for (int d = 0; d < 3; ++d) c.sym[d] = x->p.bc[d] == SBLI_BC_SYMMETRY;
 }
 
 // z-planes per workgroup: long enough to amortise the 4R-plane pipeline fill,
@@ -158,6 +159,10 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
         return fail(nullptr, SBLI_ERR_ARG, "sbli_init: gamma must be finite and > 1");
     if (p->dtype != SBLI_F64 && p->dtype != SBLI_F32)
         return fail(nullptr, SBLI_ERR_ARG, "sbli_init: dtype must be SBLI_F64 or SBLI_F32");
+    for (int d = 0; d < 3; ++d)
+        if (p->bc[d] != SBLI_BC_PERIODIC && p->bc[d] != SBLI_BC_SYMMETRY)
+            return fail(nullptr, SBLI_ERR_ARG, "sbli_init: bc[%d] must be SBLI_BC_PERIODIC or SBLI_BC_SYMMETRY (got %d)",
+                        d, p->bc[d]);
 
     sbli_ctx* x = new (std::nothrow) sbli_ctx();
     if (!x) return fail(nullptr, SBLI_ERR_ALLOC, "sbli_init: out of host memory");
@@ -301,7 +306,8 @@ extern "C" int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]) {
     const int r = ctx->r;
 #define DIAG_LAUNCH(T, RR)                                                                                      \
     diag_partial_kernel<T, RR><<<nb, kDiagThreads, 0, ctx->stream>>>((const T*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, \
-                                                                     ctx->diag_da, gm1, ctx->diag_part)
+                                                                     ctx->diag_da, gm1, ctx->p.bc[0], ctx->p.bc[1], \
+                                                                     ctx->p.bc[2], ctx->diag_part)
     if (ctx->p.dtype == SBLI_F64) {
         if (r == 1) DIAG_LAUNCH(double, 1); else if (r == 2) DIAG_LAUNCH(double, 2);
         else if (r == 3) DIAG_LAUNCH(double, 3); else DIAG_LAUNCH(double, 4);
@@ -328,7 +334,7 @@ extern "C" int sbli_num_variants(const sbli_ctx* ctx) {
     return num_variants(ctx);
 }
 
-extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[4]) {
+extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[5]) {
     if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
     if (variant < 0 || variant >= num_variants(ctx))
         return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
@@ -337,6 +343,7 @@ extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[4]) 
     info[1] = v.ty;
     info[2] = v.pre;
     info[3] = v.rot;
+    info[4] = v.minw;
     return SBLI_OK;
 }
 

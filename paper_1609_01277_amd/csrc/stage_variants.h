@@ -12,18 +12,21 @@ namespace sbli {
 
 struct StageVariant {
     int tx, ty, pre, rot;
+    int minw;   // wavefronts per SIMD the register allocation must allow (1 = as many VGPRs as needed)
 };
 
-// X-macro lists of (TX, TY, PRE, RT) per (type, radius).  The first entry is
-// the default before tuning.
-#define SBLI_VARIANTS_D1(X) X(16, 16, 1, 0) X(16, 16, 1, 1) X(32, 8, 1, 1)
-#define SBLI_VARIANTS_D2(X) X(16, 16, 1, 0) X(16, 16, 1, 1) X(16, 16, 0, 1) X(16, 8, 1, 1) X(32, 8, 0, 0)
-#define SBLI_VARIANTS_D3(X) X(8, 8, 0, 0) X(8, 8, 1, 0) X(16, 8, 1, 0)
-#define SBLI_VARIANTS_D4(X) X(16, 4, 0, 0) X(16, 4, 1, 0) X(8, 8, 0, 0)
-#define SBLI_VARIANTS_F1(X) X(16, 16, 1, 0) X(16, 16, 1, 1) X(32, 8, 1, 1)
-#define SBLI_VARIANTS_F2(X) X(16, 8, 1, 0) X(16, 8, 1, 1) X(16, 16, 1, 0) X(16, 16, 1, 1) X(32, 8, 1, 1)
-#define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0) X(16, 16, 1, 0) X(16, 8, 1, 0)
-#define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0) X(16, 8, 1, 0) X(16, 4, 1, 0)
+// X-macro lists of (TX, TY, PRE, RT, MINW) per (type, radius).  The first entry
+// is the default before tuning.
+#define SBLI_VARIANTS_D1(X) X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1) X(16, 8, 1, 1, 2)
+#define SBLI_VARIANTS_D2(X) \
+    X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(16, 16, 0, 1, 1) X(32, 8, 0, 0, 1) X(16, 8, 1, 1, 2)
+#define SBLI_VARIANTS_D3(X) X(8, 8, 0, 0, 1) X(8, 8, 1, 0, 1) X(16, 8, 1, 0, 1)
+#define SBLI_VARIANTS_D4(X) X(16, 4, 0, 0, 1) X(16, 4, 1, 0, 1) X(8, 8, 0, 0, 1)
+#define SBLI_VARIANTS_F1(X) X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1) X(16, 8, 1, 0, 1)
+#define SBLI_VARIANTS_F2(X) \
+    X(16, 8, 1, 0, 1) X(16, 8, 1, 1, 1) X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1)
+#define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0, 1) X(16, 16, 1, 0, 1) X(16, 8, 1, 0, 1)
+#define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0, 1) X(16, 8, 1, 0, 1) X(16, 4, 1, 0, 1)
 
 // One launch: the boxes (device table), their total workgroup count, the mode
 // and the RK coefficients.
@@ -36,27 +39,27 @@ struct StageArgs {
     double dt_scale, A, B;
 };
 
-template <typename T, int R, int TX, int TY, int PRE, int RT, int MODE>
+template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int MODE>
 inline void launch_fused_cfg(const StageArgs& a, const T* qin, T* dq, T* qout) {
-    fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
+    fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
         qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
 }
 
-template <typename T, int R, int TX, int TY, int PRE, int RT>
+template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW>
 inline bool try_variant(int& k, int want, const StageArgs& a, const T* qin, T* dq, T* qout) {
     if (k++ != want) return false;
     switch (a.mode) {
-        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, RT, kModeRHS>(a, qin, dq, qout); break;
-        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, RT, kModeStage1>(a, qin, dq, qout); break;
-        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, RT, kModeStage2>(a, qin, dq, qout); break;
-        default: launch_fused_cfg<T, R, TX, TY, PRE, RT, kModeStage3>(a, qin, dq, qout); break;
+        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, kModeRHS>(a, qin, dq, qout); break;
+        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, kModeStage1>(a, qin, dq, qout); break;
+        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, kModeStage2>(a, qin, dq, qout); break;
+        default: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, kModeStage3>(a, qin, dq, qout); break;
     }
     return true;
 }
 
-#define SBLI_TRY(TX_, TY_, PRE_, RT_) \
-    if (try_variant<T, R, TX_, TY_, PRE_, RT_>(k, v, a, qin, dq, qout)) return true;
-#define SBLI_ENTRY(TX_, TY_, PRE_, RT_) StageVariant{TX_, TY_, PRE_, RT_},
+#define SBLI_TRY(TX_, TY_, PRE_, RT_, MINW_) \
+    if (try_variant<T, R, TX_, TY_, PRE_, RT_, MINW_>(k, v, a, qin, dq, qout)) return true;
+#define SBLI_ENTRY(TX_, TY_, PRE_, RT_, MINW_) StageVariant{TX_, TY_, PRE_, RT_, MINW_},
 
 template <typename T, int R>
 struct VariantSet;

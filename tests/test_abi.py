@@ -60,6 +60,16 @@ def test_init_rejects_bad_params(lib, kw, msg):
     assert msg in str(ei.value)
 
 
+def test_init_rejects_bad_boundary_condition(lib):
+    import paper_1609_01277_amd as sbli
+    p = sbli.make_params(32, bc=("symmetry", "periodic", "symmetry"))
+    assert list(p.bc) == [1, 0, 1]
+    p.bc[2] = 5
+    with pytest.raises(sbli.SbliError) as ei:
+        sbli.sbli_init(p)
+    assert ei.value.code == sbli.SBLI_ERR_ARG and "bc[2]" in str(ei.value)
+
+
 def test_init_rejects_bad_dtype_and_null(lib):
     import paper_1609_01277_amd as sbli
     p = sbli.make_params(32)
