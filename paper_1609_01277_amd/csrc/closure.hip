@@ -43,6 +43,7 @@ struct sbli_net {
     __bf16 *x = nullptr, *h1 = nullptr, *h2 = nullptr, *dy = nullptr, *d2 = nullptr, *d1 = nullptr;
     float *pre1 = nullptr, *pre2 = nullptr, *y = nullptr;
     float* wpart = nullptr;          // weight-gradient partials
+    float* bpart = nullptr;          // bias-gradient partials [kBiasWg][32]
     int wgrad_wg = 512;
     double* loss_part = nullptr;
     double* loss = nullptr;
@@ -80,7 +81,8 @@ extern "C" int sbli_net_destroy(sbli_net* net) {
         hipFree(net->L[l].Wb);
     }
     void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->stats, net->x, net->h1, net->h2,
-                    net->dy, net->d2, net->d1, net->pre1, net->pre2, net->y, net->wpart, net->loss_part, net->loss};
+                    net->dy, net->d2, net->d1, net->pre1, net->pre2, net->y, net->wpart, net->bpart, net->loss_part,
+                    net->loss};
     for (void* p : ptrs) hipFree(p);
     delete net;
     return SBLI_OK;
@@ -140,6 +142,7 @@ extern "C" int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net*
     alloc((void**)&net->pre2, sizeof(float) * NP * 32);
     alloc((void**)&net->y, sizeof(float) * NP * 8);
     alloc((void**)&net->wpart, sizeof(float) * (size_t)net->wgrad_wg * 32 * 27 * 32);
+    alloc((void**)&net->bpart, sizeof(float) * (size_t)kBiasWg * 32);
     alloc((void**)&net->loss_part, sizeof(double) * nblk(NP));
     alloc((void**)&net->loss, sizeof(double));
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
@@ -239,21 +242,31 @@ extern "C" int sbli_net_get_stats(sbli_net* net, float* host_stats) {
     return SBLI_OK;
 }
 
+// One convolution (implicit GEMM on MFMA, input staged in LDS): `in` has cpad
+// channels per point (8 or 32), epilogue EPI (see closure_kernels.h).
+template <int EPI>
+static void conv(sbli_net* net, const __bf16* in, int cpad, const __bf16* W, int Kpad, const float* bias, int batch,
+                 float* fout, __bf16* bout, const float* pre_in, int ocount, int ostride) {
+    const unsigned g = (unsigned)((int64_t)batch * net->n * (net->n / kConvTy) * (net->n / kConvTx));
+    if (cpad == 32)
+        conv_mfma_lds_kernel<EPI, 32><<<g, 256, 0, net->stream>>>(in, W, Kpad, bias, net->n, fout, bout, pre_in,
+                                                                  ocount, ostride);
+    else
+        conv_mfma_lds_kernel<EPI, 8><<<g, 256, 0, net->stream>>>(in, W, Kpad, bias, net->n, fout, bout, pre_in,
+                                                                 ocount, ostride);
+}
+
 // Forward pass of `batch` samples: x -> h1 -> h2 -> y (all in the net's buffers).
 static int forward_core(sbli_net* net, const float* q, int batch) {
     const int64_t NP = (int64_t)batch * net->P;
     standardize_kernel<<<nblk(NP), 256, 0, net->stream>>>(q, net->P, batch, net->stats, net->x);
-    const unsigned g = nblk(NP);
     const Layer* L = net->L;
-    conv_mfma_kernel<kEpiGelu><<<g, 256, 0, net->stream>>>(net->x, L[0].cpad, L[0].Wf, L[0].Kf,
-                                                           net->params + L[0].b_off, net->n, NP, net->pre1, net->h1,
-                                                           nullptr, 32, 32);
-    conv_mfma_kernel<kEpiGelu><<<g, 256, 0, net->stream>>>(net->h1, L[1].cpad, L[1].Wf, L[1].Kf,
-                                                           net->params + L[1].b_off, net->n, NP, net->pre2, net->h2,
-                                                           nullptr, 32, 32);
-    conv_mfma_kernel<kEpiLinear><<<g, 256, 0, net->stream>>>(net->h2, L[2].cpad, L[2].Wf, L[2].Kf,
-                                                             net->params + L[2].b_off, net->n, NP, net->y, nullptr,
-                                                             nullptr, L[2].cout, 8);
+    conv<kEpiGelu>(net, net->x, L[0].cpad, L[0].Wf, L[0].Kf, net->params + L[0].b_off, batch, net->pre1, net->h1,
+                   nullptr, 32, 32);
+    conv<kEpiGelu>(net, net->h1, L[1].cpad, L[1].Wf, L[1].Kf, net->params + L[1].b_off, batch, net->pre2, net->h2,
+                   nullptr, 32, 32);
+    conv<kEpiLinear>(net, net->h2, L[2].cpad, L[2].Wf, L[2].Kf, net->params + L[2].b_off, batch, net->y, nullptr,
+                     nullptr, L[2].cout, 8);
     NHIP_TRY(net, hipGetLastError());
     return SBLI_OK;
 }
@@ -275,10 +288,11 @@ static int wgrad(sbli_net* net, int l, const __bf16* in, const __bf16* dout, int
     const int64_t blocks = (int64_t)batch * net->n * net->n * (net->n / 32);
     conv_wgrad_kernel<<<net->wgrad_wg, 256, 0, net->stream>>>(in, L.cpad, dout, L.opad, net->n, blocks, L.Kpad32,
                                                               net->wpart);
-    wgrad_reduce_kernel<<<nblk(L.cout * L.cin * 27), 256, 0, net->stream>>>(net->wpart, net->wgrad_wg, L.Kpad32,
-                                                                           L.cpad, L.cin, L.cout,
-                                                                           net->grads + L.w_off);
-    bias_grad_kernel<<<L.cout, 256, 0, net->stream>>>(dout, L.opad, (int64_t)batch * net->P, net->grads + L.b_off);
+    wgrad_reduce_kernel<<<nblk(L.cout * L.Kpad32), 256, 0, net->stream>>>(net->wpart, net->wgrad_wg, L.Kpad32,
+                                                                         L.cpad, L.cin, L.cout,
+                                                                         net->grads + L.w_off);
+    bias_grad_kernel<<<kBiasWg, 256, 0, net->stream>>>(dout, L.opad, (int64_t)batch * net->P, net->bpart);
+    bias_grad_final_kernel<<<1, 256, 0, net->stream>>>(net->bpart, kBiasWg, L.cout, net->grads + L.b_off);
     NHIP_TRY(net, hipGetLastError());
     return SBLI_OK;
 }
@@ -296,12 +310,10 @@ extern "C" int sbli_net_gradients(sbli_net* net, const float* q, const float* ta
     sum_doubles_kernel<<<1, 256, 0, net->stream>>>(net->loss_part, (int)g, 1.0 / (5.0 * (double)NP), net->loss);
     // layer 3
     if ((rc = wgrad(net, 2, net->h2, net->dy, batch)) != SBLI_OK) return rc;
-    conv_mfma_kernel<kEpiDGelu><<<g, 256, 0, net->stream>>>(net->dy, L[2].opad, L[2].Wb, L[2].Kb, nullptr, net->n, NP,
-                                                            nullptr, net->d2, net->pre2, 32, 32);
+    conv<kEpiDGelu>(net, net->dy, L[2].opad, L[2].Wb, L[2].Kb, nullptr, batch, nullptr, net->d2, net->pre2, 32, 32);
     // layer 2
     if ((rc = wgrad(net, 1, net->h1, net->d2, batch)) != SBLI_OK) return rc;
-    conv_mfma_kernel<kEpiDGelu><<<g, 256, 0, net->stream>>>(net->d2, L[1].opad, L[1].Wb, L[1].Kb, nullptr, net->n, NP,
-                                                            nullptr, net->d1, net->pre1, 32, 32);
+    conv<kEpiDGelu>(net, net->d2, L[1].opad, L[1].Wb, L[1].Kb, nullptr, batch, nullptr, net->d1, net->pre1, 32, 32);
     // layer 1
     if ((rc = wgrad(net, 0, net->x, net->d1, batch)) != SBLI_OK) return rc;
     NHIP_TRY(net, hipGetLastError());

@@ -139,57 +139,75 @@ __global__ void __launch_bounds__(256) destandardize_kernel(const float* __restr
 // ---------------------------------------------------------------------------
 // Implicit-GEMM convolution on MFMA (v_mfma_f32_32x32x16_bf16).
 //   out[b][p][o] = sum_kk W[o][kk] * in[b][p + off(tap(kk))][c(kk)]
-// A wave computes 2 tiles of 32 points x 32 output channels; a workgroup of 4
-// waves covers 256 consecutive points.  A operand (points x 16 kk): each lane
-// loads 8 consecutive channels of one tap at one point (16 bytes); B operand
-// (16 kk x 32 outputs): 8 consecutive kk of one output channel (16 bytes) from
-// the packed weights Wp[32][Kpad].
+// A wave computes 2 tiles of 32 points x 32 output channels.  A operand
+// (points x 16 kk): each lane reads 8 consecutive channels of one tap at one
+// point (16 bytes); B operand (16 kk x 32 outputs): 8 consecutive kk of one
+// output channel (16 bytes) from the packed weights Wp[32][Kpad].
 // Epilogues:
 //   kEpiGelu   : v = acc + bias; pre[..][o] = v (FP32, 32 ch); act[..][o] = bf16(gelu v)
 //   kEpiLinear : v = acc + bias; y[..][o] = v (FP32, ostride ch) for o < ocount
 //   kEpiDGelu  : v = acc * gelu'(pre[..][o]); act[..][o] = bf16(v) (32 ch)
 enum { kEpiGelu = 0, kEpiLinear = 1, kEpiDGelu = 2 };
 
-template <int EPI>
-__global__ void __launch_bounds__(256) conv_mfma_kernel(const __bf16* __restrict__ in, int cpad,
-                                                        const __bf16* __restrict__ Wp, int Kpad,
-                                                        const float* __restrict__ bias, int n, int64_t npts,
-                                                        float* __restrict__ fout, __bf16* __restrict__ bout,
-                                                        const float* __restrict__ pre_in, int ocount, int ostride) {
+// The input is staged in LDS (grids with n % 32 == 0).  A workgroup owns 32
+// x-points x 8 y-rows of one z-plane of one sample (256 points; wave w takes
+// rows 2w and 2w + 1 as its two 32-point M tiles).  The
+// 34 x 10 x 3 input points it reads (periodic halo of one point) are loaded
+// once into LDS and every one of the 27 taps reads its A operands from there,
+// instead of from global memory 27 times.  LDS point stride: cpad + 8 channels
+// for cpad = 32 (80 bytes: eight lanes' 16-byte reads fall in distinct banks),
+// cpad for cpad = 8.
+constexpr int kConvTx = 32, kConvTy = 8;
+constexpr int kConvHx = kConvTx + 2, kConvHy = kConvTy + 2;
+
+template <int EPI, int CPAD>
+__global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __restrict__ in, const __bf16* __restrict__ Wp,
+                                                            int Kpad, const float* __restrict__ bias, int n,
+                                                            float* __restrict__ fout, __bf16* __restrict__ bout,
+                                                            const float* __restrict__ pre_in, int ocount, int ostride) {
+    constexpr int LS = CPAD == 32 ? 40 : CPAD;                 // LDS point stride (elements)
+    __shared__ __attribute__((aligned(16))) __bf16 sx[3 * kConvHy * kConvHx * LS];
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int row = lane & 31, half = lane >> 5;
     const int64_t P = (int64_t)n * n * n;
-    const int64_t base = (int64_t)blockIdx.x * 256 + wave * 64;
-    const int row = lane & 31;       // point within an M tile (A) / output channel (B)
-    const int half = lane >> 5;      // which 8 of the 16 kk this lane supplies
-    int px[2], py[2], pz[2];
-    int64_t pb[2];                   // b * P (sample base)
-    bool valid[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int64_t g = base + t * 32 + row;
-        valid[t] = g < npts;
-        const int64_t gg = valid[t] ? g : 0;
-        pb[t] = (gg / P) * P;
-        const int64_t p = gg % P;
-        px[t] = (int)(p % n);
-        py[t] = (int)((p / n) % n);
-        pz[t] = (int)(p / ((int64_t)n * n));
+    // tile -> (sample, z, y0, x0)
+    const int tx = n / kConvTx, ty = n / kConvTy;
+    int t = blockIdx.x;
+    const int x0 = (t % tx) * kConvTx;
+    t /= tx;
+    const int y0 = (t % ty) * kConvTy;
+    t /= ty;
+    const int z = t % n;
+    const int64_t b = t / n;
+    const __bf16* inb = in + b * P * CPAD;
+    // stage the halo box: 3 x 10 x 34 points, CPAD / 8 16-byte loads each
+    constexpr int G = CPAD / 8;
+    for (int i = threadIdx.x; i < 3 * kConvHy * kConvHx * G; i += 256) {
+        const int g = i % G;
+        const int pt = i / G;
+        const int hx = pt % kConvHx, hy = (pt / kConvHx) % kConvHy, hz = pt / (kConvHx * kConvHy);
+        const int gx = wrapn(x0 + hx - 1, n), gy = wrapn(y0 + hy - 1, n), gz = wrapn(z + hz - 1, n);
+        const bf16x8 v = *(const bf16x8*)(inb + (((int64_t)gz * n + gy) * n + gx) * CPAD + g * 8);
+        *(bf16x8*)(&sx[pt * LS + g * 8]) = v;
     }
+    __syncthreads();
     floatx16 acc0 = {0}, acc1 = {0};
     const __bf16* wrow = Wp + (int64_t)row * Kpad;
-    const int ntap_k = 27 * cpad;
+    const int ntap_k = 27 * CPAD;
+    const int ry0 = 2 * wave;                             // tile rows ry0, ry0 + 1 of the two M tiles
+#pragma unroll 4
     for (int k0 = 0; k0 < Kpad; k0 += 16) {
         const int kk = k0 + half * 8;
         const bf16x8 bv = *(const bf16x8*)(wrow + kk);
         bf16x8 a0, a1;
         if (kk < ntap_k) {
-            const int tap = kk / cpad, c = kk % cpad;
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int64_t q0 = pb[0] + ((int64_t)wrapn(pz[0] + dz, n) * n + wrapn(py[0] + dy, n)) * n + wrapn(px[0] + dx, n);
-            const int64_t q1 = pb[1] + ((int64_t)wrapn(pz[1] + dz, n) * n + wrapn(py[1] + dy, n)) * n + wrapn(px[1] + dx, n);
-            a0 = *(const bf16x8*)(in + q0 * cpad + c);
-            a1 = *(const bf16x8*)(in + q1 * cpad + c);
+            const int tap = kk / CPAD, c = kk % CPAD;
+            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo-box offsets (0..2)
+            const int p0 = (dz * kConvHy + ry0 + dy) * kConvHx + row + dx;
+            const int p1 = p0 + kConvHx;                               // next row
+            a0 = *(const bf16x8*)(&sx[p0 * LS + c]);
+            a1 = *(const bf16x8*)(&sx[p1 * LS + c]);
         } else {
 #pragma unroll
             for (int j = 0; j < 8; ++j) { a0[j] = (__bf16)0.0f; a1[j] = (__bf16)0.0f; }
@@ -197,16 +215,16 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(const __bf16* __restrict
         acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, bv, acc0, 0, 0, 0);
         acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, bv, acc1, 0, 0, 0);
     }
-    // D[m][o]: o = lane & 31, m = (j / 4) * 8 + (lane >> 5) * 4 + (j & 3)
+    // D[m][o]: o = lane & 31, m = (j / 4) * 8 + (lane >> 5) * 4 + (j & 3); m = x within the row
     const int o = row;
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const floatx16 acc = t == 0 ? acc0 : acc1;
+    for (int tt = 0; tt < 2; ++tt) {
+        const floatx16 acc = tt == 0 ? acc0 : acc1;
+        const int y = y0 + 2 * wave + tt;
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int m = (j / 4) * 8 + half * 4 + (j & 3);
-            const int64_t g = base + t * 32 + m;
-            if (g >= npts) continue;
+            const int64_t g = b * P + ((int64_t)z * n + y) * n + x0 + m;
             if (EPI == kEpiGelu) {
                 const float v = acc[j] + bias[o];
                 fout[g * 32 + o] = v;
@@ -319,32 +337,77 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const __bf16* __restric
 // a layer in the master layout dW[o][c][tap] (o < cout, c < cin).
 __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int nwg, int Kpad32,
                                                            int cpad, int cin, int cout, float* __restrict__ dW) {
+    // one thread per (o, kk), kk = tap * cpad + c fastest, so the partial rows
+    // are read contiguously.  Four interleaved accumulators (partials w = 4i + j
+    // into s_j) keep four loads in flight; they are combined in a fixed order,
+    // so the result is deterministic.
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    const int total = cout * cin * 27;
-    if (id >= total) return;
-    const int tap = id % 27;
-    const int c = (id / 27) % cin;
-    const int o = id / (27 * cin);
-    const int kk = tap * cpad + c;
-    float s = 0.0f;
-    for (int w = 0; w < nwg; ++w) s += part[((int64_t)w * 32 + o) * Kpad32 + kk];
-    dW[id] = s;
+    const int kk = id % Kpad32;
+    const int o = id / Kpad32;
+    if (o >= cout) return;
+    const int tap = kk / cpad, c = kk % cpad;
+    if (tap >= 27 || c >= cin) return;
+    const float* p = part + (int64_t)o * Kpad32 + kk;
+    const int64_t stride = (int64_t)32 * Kpad32;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int w = 0;
+    for (; w + 4 <= nwg; w += 4) {
+        s0 += p[(w + 0) * stride];
+        s1 += p[(w + 1) * stride];
+        s2 += p[(w + 2) * stride];
+        s3 += p[(w + 3) * stride];
+    }
+    for (; w < nwg; ++w) s0 += p[w * stride];
+    dW[(o * cin + c) * 27 + tap] = (s0 + s1) + (s2 + s3);
 }
 
-// Bias gradient db[o] = sum_p dout[p][o] (one block per output channel).
+// Bias gradient db[o] = sum_p dout[p][o], in two deterministic passes.
+// Pass 1: workgroup w sums points [w * chunk, (w + 1) * chunk) into
+// part[w][32]; each thread reads 8 channels of a point with one 16-byte load
+// (opad / 8 threads per point, 256 / (opad / 8) point lanes), and the point
+// lanes are combined in LDS in a fixed order.
+constexpr int kBiasWg = 512;
 __global__ void __launch_bounds__(256) bias_grad_kernel(const __bf16* __restrict__ dout, int opad, int64_t npts,
-                                                        float* __restrict__ db) {
-    const int o = blockIdx.x;
-    float s = 0.0f;
-    for (int64_t p = threadIdx.x; p < npts; p += blockDim.x) s += (float)dout[p * opad + o];
-    __shared__ float ss[256];
-    ss[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) ss[threadIdx.x] += ss[threadIdx.x + w];
-        __syncthreads();
+                                                        float* __restrict__ part) {
+    const int groups = opad / 8;                     // 1 or 4
+    const int cg = threadIdx.x % groups, pl = threadIdx.x / groups;
+    const int lanes = 256 / groups;
+    const int64_t chunk = (npts + gridDim.x - 1) / gridDim.x;
+    const int64_t p0 = (int64_t)blockIdx.x * chunk;
+    const int64_t p1 = p0 + chunk < npts ? p0 + chunk : npts;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t p = p0 + pl; p < p1; p += lanes) {
+        const bf16x8 v = *(const bf16x8*)(dout + p * opad + cg * 8);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += (float)v[j];
     }
-    if (threadIdx.x == 0) db[o] = ss[0];
+    __shared__ float ss[256][9];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) ss[threadIdx.x][j] = s[j];
+    __syncthreads();
+    if ((int)threadIdx.x < opad) {
+        const int c = threadIdx.x, g = c / 8, j = c % 8;
+        float t = 0.0f;
+        for (int l = 0; l < lanes; ++l) t += ss[l * groups + g][j];
+        part[blockIdx.x * 32 + c] = t;
+    }
+}
+
+// Pass 2: 256 threads = 32 channels x 8 slices; slice k sums partials
+// w = k, k + 8, ...; the slices are combined in order.
+__global__ void __launch_bounds__(256) bias_grad_final_kernel(const float* __restrict__ part, int nwg, int cout,
+                                                              float* __restrict__ db) {
+    const int o = threadIdx.x & 31, k = threadIdx.x >> 5;
+    float s = 0.0f;
+    for (int w = k; w < nwg; w += 8) s += part[w * 32 + o];
+    __shared__ float ss[8][32];
+    ss[k][o] = s;
+    __syncthreads();
+    if ((int)threadIdx.x < cout) {
+        float t = 0.0f;
+        for (int j = 0; j < 8; ++j) t += ss[j][threadIdx.x];
+        db[threadIdx.x] = t;
+    }
 }
 
 // MSE between the network output y [B][P][8] (5 used) and the standardised

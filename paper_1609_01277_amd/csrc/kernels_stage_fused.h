@@ -179,7 +179,7 @@ struct DirSums {
 // register window instead of shifting it (for windows of at most 7 planes).
 // clos (may be null): a closure term with the state's planar layout, added to
 // the residual when *cflag != 0.
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT>
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int SYM>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
                                                  T B, const T* __restrict__ clos, const int* __restrict__ cflag) {
@@ -221,8 +221,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     }
     // Periodic axes wrap; symmetry axes mirror, and a mirrored column carries the
     // sign-bit mask of the momentum component normal to that boundary.
+    // SYM = 0 compiles the periodic case only (no masks, no sign flips).
+    const int symx = SYM ? c.sym[0] : 0, symy = SYM ? c.sym[1] : 0, symz = SYM ? c.sym[2] : 0;
     unsigned fcx, fcy;
-    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fcy) * nx + fold_index(x0 + cx, nx, c.sym[0], fcx);
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, symy, fcy) * nx + fold_index(x0 + cx, nx, symx, fcx);
     const bool store = interior && (x0 + cx < nx) && (y0 + cy < ny);
 
     // u-only ring point of this thread (if any): E2 minus E1.
@@ -252,7 +254,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
         }
     }
     unsigned fox, foy;
-    const int64_t ocol = (int64_t)fold_index(y0 + oy, ny, c.sym[1], foy) * nx + fold_index(x0 + ox, nx, c.sym[0], fox);
+    const int64_t ocol = (int64_t)fold_index(y0 + oy, ny, symy, foy) * nx + fold_index(x0 + ox, nx, symx, fox);
 
     // ---- register windows ----
     constexpr int W = 3 * R + 1;
@@ -270,7 +272,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     // images beyond a z symmetry boundary).  The loaded values stay untouched
     // until they are used, so a prefetch never waits for its data.
     unsigned pqz = 0u, prz = 0u;
-    const int symz = c.sym[2];   // planes stay within [-2R, nz + 2R): one mirror or wrap at most
+    // planes stay within [-2R, nz + 2R): one mirror or wrap at most
     T pd0 = 0, pd1 = 0, pd2 = 0, pd3 = 0, pd4 = 0;   // next dq (own column)
     auto issue = [&](int it) {
         const int L = z0 - 2 * R + it;
@@ -506,7 +508,8 @@ struct BoxInst {
 // neighbouring tiles, whose halos then hit in that L2.
 // MINW: the fewest wavefronts per SIMD the register allocation must allow
 // (2 caps a thread at 256 VGPRs, so two 4-wavefront workgroups share a CU).
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW>
+// SYM: 1 for boxes with a symmetry axis, 0 for periodic boxes.
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW, int SYM>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                        const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
@@ -528,7 +531,7 @@ __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     const int z0 = chunk * b.zchunk;
     const int zc = min(b.zchunk, b.c.n[2] - z0);
     T* dqb = dq ? dq + b.offset : nullptr;
-    fused_stage_body<T, R, TX, TY, MODE, PRE, RT>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
+    fused_stage_body<T, R, TX, TY, MODE, PRE, RT, SYM>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
                                               b.dt * dt_scale, A, B, b.closure, b.cflag);
 }
 

@@ -242,7 +242,8 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
 }
 
 static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
-    const StageArgs a{ctx->stream, ctx->inst_dev, 1, total_wg(ctx), mode, dt, A, B};
+    const int sym = ctx->p.bc[0] | ctx->p.bc[1] | ctx->p.bc[2];
+    const StageArgs a{ctx->stream, ctx->inst_dev, 1, total_wg(ctx), mode, dt, A, B, sym};
     if (ctx->p.dtype == SBLI_F64)
         StageDispatch<double>::launch(ctx->r, ctx->variant, a, (const double*)qin, (double*)dq, (double*)qout);
     else
@@ -514,7 +515,7 @@ static int batch_build_table(sbli_batch* b) {
 }
 
 static void batch_launch_stage(sbli_batch* b, hipStream_t s, const void* qin, void* dq, void* qout, int k) {
-    const StageArgs a{s, b->table_dev, b->count, b->total_wg, kModeStage1 + k, 1.0, kRK_A[k], kRK_B[k]};
+    const StageArgs a{s, b->table_dev, b->count, b->total_wg, kModeStage1 + k, 1.0, kRK_A[k], kRK_B[k], 0};
     if (b->dtype == SBLI_F64)
         StageDispatch<double>::launch(b->r, b->variant, a, (const double*)qin, (double*)dq, (double*)qout);
     else

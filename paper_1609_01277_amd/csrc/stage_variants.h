@@ -24,7 +24,7 @@ struct StageVariant {
 #define SBLI_VARIANTS_D4(X) X(16, 4, 0, 0, 1) X(16, 4, 1, 0, 1) X(8, 8, 0, 0, 1)
 #define SBLI_VARIANTS_F1(X) X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1) X(16, 8, 1, 0, 1)
 #define SBLI_VARIANTS_F2(X) \
-    X(16, 8, 1, 0, 1) X(16, 8, 1, 1, 1) X(16, 16, 1, 0, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1)
+    X(16, 8, 1, 0, 1) X(16, 8, 1, 1, 1) X(16, 16, 1, 1, 1) X(32, 8, 1, 1, 1) X(32, 8, 1, 1, 3) X(16, 16, 1, 1, 3)
 #define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0, 1) X(16, 16, 1, 0, 1) X(16, 8, 1, 0, 1)
 #define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0, 1) X(16, 8, 1, 0, 1) X(16, 4, 1, 0, 1)
 
@@ -37,12 +37,19 @@ struct StageArgs {
     int total_wg;
     int mode;
     double dt_scale, A, B;
+    int sym;            // 1 if a box of the launch has a symmetry axis
 };
 
 template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int MODE>
 inline void launch_fused_cfg(const StageArgs& a, const T* qin, T* dq, T* qout) {
-    fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0, a.stream>>>(
-        qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
+    if (a.sym)
+        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 1><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0,
+                                                                   a.stream>>>(
+            qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
+    else
+        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 0><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT, 0,
+                                                                   a.stream>>>(
+            qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
 }
 
 template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW>
