@@ -19,7 +19,16 @@
 //      windows, the residual, and the RK update written straight to HBM.
 // Columns of the R-ring around the tile are handled by extra "halo" threads
 // (whole wavefronts apart from the interior ones); the 2R-ring of u needed only
-// for the x/y gradient stencils of halo columns is loaded directly.  Periodic
+// for the x/y gradient stencils of halo columns is loaded directly.
+//
+// Two barrier schedules.  DB = 0: step 1 | barrier | step 2 | barrier | step 3,
+// each LDS plane single-buffered.  DB = 1: the LDS planes of u and of the point
+// fields alternate between two buffers by iteration parity and the point fields
+// of the output plane are stored in step 1.  Step 3 then reads nothing that
+// another thread writes in the same iteration (the z-nested fields of the newest
+// gradient plane belong to the thread's own column), so one barrier per
+// iteration suffices: the residual of plane o overlaps the gradients and, in the
+// halo wavefronts, the loads of the next iteration.  Periodic
 // wrap (or, on a symmetry axis, the mirror image with the normal momentum
 // negated) is folded into the column and plane coordinates, so ragged tiles and
 // boundaries need no special case beyond masking the stores.
@@ -102,6 +111,24 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// n stores that the hardware drops (a buffer descriptor of one element and an
+// offset beyond it): they keep the count of memory operations equal on both
+// sides of a branch (see step 4 of fused_stage_body).
+constexpr int kDropOff = (int)0x80000000;
+constexpr int kBufferWord3 = 0x00020000;   // descriptor word 3 of a raw (untyped) buffer
+typedef int sbli_v2i __attribute__((ext_vector_type(2)));
+template <int N, typename T>
+__device__ __forceinline__ void dropped_stores(T* any) {
+    const __amdgpu_buffer_rsrc_t d = __builtin_amdgcn_make_buffer_rsrc(any, 0, (int)sizeof(T), kBufferWord3);
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        if constexpr (sizeof(T) == 8)
+            __builtin_amdgcn_raw_buffer_store_b64(sbli_v2i{0, 0}, d, kDropOff, 0, 0);
+        else
+            __builtin_amdgcn_raw_buffer_store_b32(0, d, kDropOff, 0, 0);
+    }
+}
+
 __device__ __forceinline__ int wrap_mod(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
@@ -173,19 +200,20 @@ struct DirSums {
 };
 
 // One workgroup = one (x, y) tile and one z-chunk [z0, z0 + zc).
-// PRE selects how far global loads run ahead of their use: 0 = loaded where used,
-// 1 = the state of the next plane and the next u-ring point are requested one
-// iteration early, 2 = dq of the next output plane as well.  RT = 1 rotates the
-// register window instead of shifting it (for windows of at most 7 planes).
+// PRE: whether the state of the entering plane and of the u-ring point is
+// requested one iteration ahead (1) or in the iteration itself (0).  RT = 1
+// rotates the register window instead of shifting it (for windows of at most 7
+// planes).
 // clos (may be null): a closure term with the state's planar layout, added to
 // the residual when *cflag != 0.
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int SYM>
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int SYM, int DB>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
                                                  T B, const T* __restrict__ clos, const int* __restrict__ cflag) {
     using S = FusedShape<R, TX, TY>;
-    __shared__ T s_u[3][S::BY2][S::BX2];
-    __shared__ T s_pl[kPlFields][S::BY1][S::BX1];
+    constexpr int NB = DB ? 2 : 1;     // buffers of the u plane and the point-field plane
+    __shared__ T s_u[NB][3][S::BY2][S::BX2];
+    __shared__ T s_pl[NB][kPlFields][S::BY1][S::BX1];
     // Rings of the nested-derivative fields, indexed by iteration: (V_x, Th_x,
     // V_y, Th_y) of the last R+1 gradient planes over the tile and its R-ring,
     // and (V_z, Th_z) of the last 2R+1 gradient planes over the tile.
@@ -264,7 +292,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     for (int s = 0; s <= 3 * R; ++s) Qb[s] = PF<T>{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
     const int iters = zc + 4 * R;
-    // With PRE > 0 the loads of iteration it+1 are issued before the work of
+    // With PRE = 1 the loads of iteration it+1 are issued before the work of
     // iteration it starts, and consumed one iteration later.
     T pq0 = 0, pq1 = 0, pq2 = 0, pq3 = 0, pq4 = 0;   // next q (own column)
     T pr0 = 1, pr1 = 0, pr2 = 0, pr3 = 0;            // next ring point (rho, rho u_i)
@@ -272,32 +300,26 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     // images beyond a z symmetry boundary).  The loaded values stay untouched
     // until they are used, so a prefetch never waits for its data.
     unsigned pqz = 0u, prz = 0u;
-    // planes stay within [-2R, nz + 2R): one mirror or wrap at most
-    T pd0 = 0, pd1 = 0, pd2 = 0, pd3 = 0, pd4 = 0;   // next dq (own column)
+    // planes stay within [-2R, nz + 2R): one mirror or wrap at most.  Every lane
+    // loads in every iteration, from an in-range point (a lane without a column
+    // reads the tile's first column; its values are unused).
     auto issue = [&](int it) {
         const int L = z0 - 2 * R + it;
-        if (e1) {
-            const int64_t idx = (int64_t)map_index(L, nz, symz, pqz) * plane + col;
-            pq0 = q[idx];
-            pq1 = q[P + idx];
-            pq2 = q[2 * P + idx];
-            pq3 = q[3 * P + idx];
-            pq4 = q[4 * P + idx];
+        {
+            const T* b = q + (int64_t)map_index(L, nz, symz, pqz) * plane + col;
+            pq0 = b[0];
+            pq1 = b[P];
+            pq2 = b[2 * P];
+            pq3 = b[3 * P];
+            pq4 = b[4 * P];
         }
-        if (has_out && it >= 2 * R) {
-            const int64_t idx = (int64_t)map_index(L - R, nz, symz, prz) * plane + ocol;
-            pr0 = q[idx];
-            pr1 = q[P + idx];
-            pr2 = q[2 * P + idx];
-            pr3 = q[3 * P + idx];
-        }
-        if (PRE == 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store && it >= 4 * R) {
-            const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
-            pd0 = dq[idx];
-            pd1 = dq[P + idx];
-            pd2 = dq[2 * P + idx];
-            pd3 = dq[3 * P + idx];
-            pd4 = dq[4 * P + idx];
+        {
+            // the ring plane L - R is needed from the first gradient plane on
+            const T* b = q + (int64_t)map_index(it >= 2 * R ? L - R : L, nz, symz, prz) * plane + ocol;
+            pr0 = b[0];
+            pr1 = b[P];
+            pr2 = b[2 * P];
+            pr3 = b[3 * P];
         }
     };
     if (PRE > 0) issue(0);
@@ -308,12 +330,13 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
         constexpr int PH = decltype(ph)::value;
         auto slot = [](int k) { return ROT ? (k + PH) % W : k; };
             const int L = z0 - 2 * R + it;           // plane loaded this iteration
+            const int bsel = DB ? (it & 1) : 0;      // LDS buffer of this iteration's planes
             if (PRE == 0) issue(it);
             const T cq0 = pq0, cq1 = flip_sign(pq1, fcx), cq2 = flip_sign(pq2, fcy), cq3 = flip_sign(pq3, pqz),
                     cq4 = pq4;
             const T cr0 = pr0, cr1 = flip_sign(pr1, fox), cr2 = flip_sign(pr2, foy), cr3 = flip_sign(pr3, prz);
-            T cd[5] = {pd0, pd1, pd2, pd3, pd4};
             if (PRE > 0 && it + 1 < iters) issue(it + 1);
+            __builtin_amdgcn_sched_barrier(0);
             // 1. plane L enters the window
             if (e1) {
                 const PF<T> f = make_pf<T>(cq0, cq1, cq2, cq3, cq4, c.gm1, c.gM2);
@@ -328,19 +351,35 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
             // 2. LDS plane of u at the gradient plane a = L - R
             if (do_grad) {
                 if (e1) {
-                    s_u[0][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u0;
-                    s_u[1][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u1;
-                    s_u[2][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u2;
+                    s_u[bsel][0][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u0;
+                    s_u[bsel][1][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u1;
+                    s_u[bsel][2][cy + 2 * R][cx + 2 * R] = Qb[slot(2 * R)].u2;
                 }
                 if (has_out) {
                     const T rr = fast_recip(cr0);
-                    s_u[0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
-                    s_u[1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
-                    s_u[2][oy + 2 * R][ox + 2 * R] = cr3 * rr;
+                    s_u[bsel][0][oy + 2 * R][ox + 2 * R] = cr1 * rr;
+                    s_u[bsel][1][oy + 2 * R][ox + 2 * R] = cr2 * rr;
+                    s_u[bsel][2][oy + 2 * R][ox + 2 * R] = cr3 * rr;
                 }
             }
+            // LDS plane of point fields at the output plane o = L - 2R
+            auto store_pl = [&]() {
+                const PF<T>& f = Qb[slot(R)];
+                const int ly = cy + R, lx = cx + R;
+                s_pl[bsel][0][ly][lx] = f.rho;
+                s_pl[bsel][1][ly][lx] = f.m0;
+                s_pl[bsel][2][ly][lx] = f.m1;
+                s_pl[bsel][3][ly][lx] = f.m2;
+                s_pl[bsel][4][ly][lx] = f.E;
+                s_pl[bsel][5][ly][lx] = f.u0;
+                s_pl[bsel][6][ly][lx] = f.u1;
+                s_pl[bsel][7][ly][lx] = f.u2;
+                s_pl[bsel][8][ly][lx] = f.p;
+                s_pl[bsel][9][ly][lx] = f.Tm;
+            };
+            if (DB && do_out && e1) store_pl();
             __syncthreads();
-            // 3. velocity gradient at plane a -> nested fields; LDS plane of point fields at o
+            // 3. velocity gradient at plane a -> nested fields
             if (do_grad && e1) {
                 T g[3][3];
     #pragma unroll
@@ -348,8 +387,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     T sx = 0, sy = 0, sz = 0;
     #pragma unroll
                     for (int m = 1; m <= R; ++m) {
-                        sx = fmaT(c.da[0][m - 1], s_u[b][cy + 2 * R][cx + 2 * R + m] - s_u[b][cy + 2 * R][cx + 2 * R - m], sx);
-                        sy = fmaT(c.da[1][m - 1], s_u[b][cy + 2 * R + m][cx + 2 * R] - s_u[b][cy + 2 * R - m][cx + 2 * R], sy);
+                        sx = fmaT(c.da[0][m - 1],
+                                  s_u[bsel][b][cy + 2 * R][cx + 2 * R + m] - s_u[bsel][b][cy + 2 * R][cx + 2 * R - m], sx);
+                        sy = fmaT(c.da[1][m - 1],
+                                  s_u[bsel][b][cy + 2 * R + m][cx + 2 * R] - s_u[bsel][b][cy + 2 * R - m][cx + 2 * R], sy);
                         const T up = b == 0 ? Qb[slot(2 * R + m)].u0 : (b == 1 ? Qb[slot(2 * R + m)].u1 : Qb[slot(2 * R + m)].u2);
                         const T um = b == 0 ? Qb[slot(2 * R - m)].u0 : (b == 1 ? Qb[slot(2 * R - m)].u1 : Qb[slot(2 * R - m)].u2);
                         sz = fmaT(c.da[2][m - 1], up - um, sz);
@@ -379,45 +420,42 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 s_axy[sxy][3][cy + R][cx + R] = theta - g[1][1];
                 if (interior) {
                     const int sz = it % (2 * R + 1);
-                    s_az[sz][0][cy][cx] = V[2];
+                    s_az[sz][0][cy][cx] = V[2];   // read back only by this thread
                     s_az[sz][1][cy][cx] = theta - g[2][2];
                 }
             }
-            if (do_out && e1) {
-                const PF<T>& f = Qb[slot(R)];
-                const int ly = cy + R, lx = cx + R;
-                s_pl[0][ly][lx] = f.rho;
-                s_pl[1][ly][lx] = f.m0;
-                s_pl[2][ly][lx] = f.m1;
-                s_pl[3][ly][lx] = f.m2;
-                s_pl[4][ly][lx] = f.E;
-                s_pl[5][ly][lx] = f.u0;
-                s_pl[6][ly][lx] = f.u1;
-                s_pl[7][ly][lx] = f.u2;
-                s_pl[8][ly][lx] = f.p;
-                s_pl[9][ly][lx] = f.Tm;
+            if (!DB) {
+                if (do_out && e1) store_pl();
+                __syncthreads();
             }
-            __syncthreads();
-            // 4. residual and RK update at the output plane o = L - 2R
+            // 4. residual and RK update at the output plane o = L - 2R.  The global
+            // accesses of this step sit in branches (output lanes, ragged tiles),
+            // and the counter that loads are waited on also counts stores: a path
+            // that skips them is padded with as many dropped stores, so that the
+            // compiler's wait for the next prefetched plane never has to cover
+            // this iteration's stores.
+            constexpr int NLD = (MODE == kModeStage2 || MODE == kModeStage3) ? 5 : 0;
+            constexpr int NST = (MODE == kModeRHS || MODE == kModeStage3) ? 5 : 10;
             if (do_out && interior) {
                 const int ly = cy + R, lx = cx + R;
-                if (PRE < 2 && (MODE == kModeStage2 || MODE == kModeStage3) && store) {
-                    const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
+                const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
+                T cd[5] = {0, 0, 0, 0, 0};
+                if (NLD > 0) {
     #pragma unroll
                     for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
                 }
                 auto ld = [&](int yy, int xx) {
                     PF<T> f;
-                    f.rho = s_pl[0][yy][xx];
-                    f.m0 = s_pl[1][yy][xx];
-                    f.m1 = s_pl[2][yy][xx];
-                    f.m2 = s_pl[3][yy][xx];
-                    f.E = s_pl[4][yy][xx];
-                    f.u0 = s_pl[5][yy][xx];
-                    f.u1 = s_pl[6][yy][xx];
-                    f.u2 = s_pl[7][yy][xx];
-                    f.p = s_pl[8][yy][xx];
-                    f.Tm = s_pl[9][yy][xx];
+                    f.rho = s_pl[bsel][0][yy][xx];
+                    f.m0 = s_pl[bsel][1][yy][xx];
+                    f.m1 = s_pl[bsel][2][yy][xx];
+                    f.m2 = s_pl[bsel][3][yy][xx];
+                    f.E = s_pl[bsel][4][yy][xx];
+                    f.u0 = s_pl[bsel][5][yy][xx];
+                    f.u1 = s_pl[bsel][6][yy][xx];
+                    f.u2 = s_pl[bsel][7][yy][xx];
+                    f.p = s_pl[bsel][8][yy][xx];
+                    f.Tm = s_pl[bsel][9][yy][xx];
                     return f;
                 };
                 const PF<T>& s = Qb[slot(R)];
@@ -454,7 +492,6 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
                 }
                 if (store) {
-                    const int64_t idx = (int64_t)(L - 2 * R) * plane + col;   // output planes lie inside the box
                     T Rv[5] = {Rr, R0, R1, R2, RE};
                     if (clos != nullptr && cflag[0] != 0) {
     #pragma unroll
@@ -472,8 +509,13 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                             out[f * P + idx] = fmaT(B, dn, qv[f]);
                         }
                     }
+                } else {
+                    dropped_stores<NST>(out);
                 }
+            } else {
+                dropped_stores<NLD + NST>(out);
             }
+            __builtin_amdgcn_sched_barrier(0);
     };
     if constexpr (ROT) {
         for (int it0 = 0; it0 < iters; it0 += W) {
@@ -509,7 +551,8 @@ struct BoxInst {
 // MINW: the fewest wavefronts per SIMD the register allocation must allow
 // (2 caps a thread at 256 VGPRs, so two 4-wavefront workgroups share a CU).
 // SYM: 1 for boxes with a symmetry axis, 0 for periodic boxes.
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW, int SYM>
+// DB: barrier schedule (see fused_stage_body).
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW, int SYM, int DB>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                        const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
@@ -531,7 +574,7 @@ __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     const int z0 = chunk * b.zchunk;
     const int zc = min(b.zchunk, b.c.n[2] - z0);
     T* dqb = dq ? dq + b.offset : nullptr;
-    fused_stage_body<T, R, TX, TY, MODE, PRE, RT, SYM>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
+    fused_stage_body<T, R, TX, TY, MODE, PRE, RT, SYM, DB>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
                                               b.dt * dt_scale, A, B, b.closure, b.cflag);
 }
 

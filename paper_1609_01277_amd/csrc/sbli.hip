@@ -335,7 +335,7 @@ extern "C" int sbli_num_variants(const sbli_ctx* ctx) {
     return num_variants(ctx);
 }
 
-extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[5]) {
+extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[6]) {
     if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
     if (variant < 0 || variant >= num_variants(ctx))
         return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
@@ -345,6 +345,7 @@ extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[5]) 
     info[2] = v.pre;
     info[3] = v.rot;
     info[4] = v.minw;
+    info[5] = v.db;
     return SBLI_OK;
 }
 
