@@ -7,7 +7,7 @@ paper's time step for that grid (3.385e-3 at 64^3, halved per doubling).  A step
 is one pass of the whole hot path: three fused residual + RK-update stages over
 the full grid.  The state starts resident in HBM.
 
-Prints ONE JSON line on stdout.  Extra measurements (FP32 state, order 8) and the
+Prints ONE JSON line on stdout.  Extra measurements (FP32 state, orders 8 and 12) and the
 CPU oracle baseline are attached to the same line.
 """
 import argparse
@@ -202,7 +202,7 @@ def main():
     ap.add_argument("--n", type=int, default=512)
     ap.add_argument("--order", type=int, default=4)
     ap.add_argument("--dtype", default="f64", choices=["f64", "f32"])
-    ap.add_argument("--no-extra", action="store_true", help="skip the FP32 and order-8 lines")
+    ap.add_argument("--no-extra", action="store_true", help="skip the FP32, order-8 and order-12 lines")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=256)
     ap.add_argument("--closure-only", action="store_true",
@@ -250,7 +250,7 @@ def main():
 
     extra = {}
     if not args.no_extra:
-        for (dt_, order) in (("f32", args.order), ("f64", 8)):
+        for (dt_, order) in (("f32", args.order), ("f64", 8), ("f64", 12)):
             if dt_ == args.dtype and order == args.order:
                 continue
             r = measure(sbli, torch, args.n, order, dt_, args.steps, args.warmup)

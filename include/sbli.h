@@ -44,7 +44,7 @@ extern "C" {
  * Problem statement (paper Sec. "Grid" and Sec. "3D Taylor-Green vortex"):
  * grid points per axis, box lengths, Reynolds, Mach and Prandtl numbers, ratio
  * of specific heats, central-difference order and the state element type.
- * Requirements: order in {2, 4, 6, 8}; every n >= 2*order + 1 (the nested
+ * Requirements: order even, 2 to 12; every n >= 2*order + 1 (the nested
  * derivative terms reach 2*(order/2) points each way); lengths, Re, Mach, Pr > 0;
  * gamma > 1; dtype SBLI_F64 or SBLI_F32.
  */
@@ -137,21 +137,28 @@ int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int 
 int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
 
 /*
- * Launch tuning of the fused stage kernel.  Each (dtype, order) has a small set
- * of compiled variants (x/y tile of a workgroup, how far the global loads
- * run ahead, how the register window advances); together with the number of z-planes per workgroup ("zchunk") they
- * fix the launch configuration.  All variants compute bitwise identical
- * results; only speed differs.
+ * Launch tuning of the stage kernel.  Each (dtype, order) up to order 8 has a
+ * small set of compiled variants of the fused stage kernel (x/y tile of a
+ * workgroup, how far the global loads run ahead, how the register window
+ * advances, the barrier schedule); together with the number of z-planes per
+ * workgroup ("zchunk") they fix the launch configuration.  The last variant of
+ * every (dtype, order) is the staged form: three point-parallel launches with the
+ * point fields (5 words per point) and the nested fields (6 words per point) in
+ * library-owned device memory, allocated when the form is first selected and
+ * kept until sbli_destroy; orders 10 and 12 have only this variant, selected at
+ * sbli_init.  All variants compute bitwise identical results; only speed differs.
  *
  * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
  * sbli_variant_info: info = {tile x, tile y, load-ahead depth, register-window
  *   rotation (1) or shifting (0), wavefronts per SIMD its register allocation
  *   allows at least (1: as many registers as the kernel wants), barrier
  *   schedule (0: two barriers per z-plane; 1: double-buffered LDS planes, one
- *   barrier)} of a variant (6 ints written).
+ *   barrier)} of a variant (6 ints written); all six are 0 for the staged form.
  * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
- *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz).  sbli_set_tuning waits
- *   for the context's stream (it updates a small device table).
+ *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz; the staged form ignores
+ *   zchunk).  sbli_set_tuning waits for the context's stream (it updates a small
+ *   device table).  Selecting the staged form may allocate its scratch
+ *   (SBLI_ERR_ALLOC if that fails; the previous selection then stays).
  * sbli_autotune: time every variant with several zchunks (hipEvents on the
  *   context's stream, `reps` RK3 steps each after one warm-up step) using the
  *   caller's device buffers, then select the fastest; *best_ms (may be NULL)
@@ -176,6 +183,7 @@ int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int 
  * Results are bitwise identical to stepping each box with its own context
  * (sbli_batch_step_sequential) in the same launch configuration.
  *
+ * Orders 2, 4, 6 and 8 (the fused stage kernel takes a table of boxes).
  * sbli_instance: n (>= 2*order+1) points per axis, Re, Mach, Pr > 0,
  *   gamma > 1, dt > 0 its time step, phase the shift of its initial state.
  * sbli_batch_init: validate and set up `count` boxes; *out receives the batch.

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libsbli.so")
-SOURCES = ["sbli.hip", "closure.hip", "scalar.hip"] + ["stage_%s_r%d.hip" % (t, r) for t in ("f64", "f32") for r in (1, 2, 3, 4)]
+SOURCES = ["sbli.hip", "closure.hip", "scalar.hip", "staged.hip"] + ["stage_%s_r%d.hip" % (t, r) for t in ("f64", "f32") for r in (1, 2, 3, 4)]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -14,6 +14,7 @@
 #include "../../include/sbli_closure.h"
 #include "kernels_pointwise.h"
 #include "stage_variants.h"
+#include "staged.h"
 #include "stencil_weights.h"
 
 using namespace sbli;
@@ -39,6 +40,7 @@ struct sbli_ctx {
     double* diag_part;      // kDiagBlocks * (2 kDiagQ + 3)
     double* diag_da;        // 3 * kMaxR weights a_m / h (double) for the vorticity
     double* diag_out;       // 10 doubles
+    void* stg;              // scratch of the staged form (kStagedScratchWords * P elements) or null
     std::string err;
 };
 
@@ -94,12 +96,29 @@ static int default_zchunk(const sbli_ctx* x) {
     return zc;
 }
 
-static int num_variants(const sbli_ctx* ctx) {
+// Variants of a context: the compiled fused variants of (dtype, order) (none
+// beyond order 8), then the staged form (all fields of the StageVariant 0).
+static int num_fused(const sbli_ctx* ctx) {
+    if (ctx->r > 4) return 0;
     return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::count(ctx->r) : StageDispatch<float>::count(ctx->r);
 }
 
+static int num_variants(const sbli_ctx* ctx) { return num_fused(ctx) + 1; }
+
+static bool is_staged(const sbli_ctx* ctx, int v) { return v == num_fused(ctx); }
+
 static StageVariant variant_of(const sbli_ctx* ctx, int v) {
+    if (is_staged(ctx, v)) return StageVariant{0, 0, 0, 0, 0, 0};
     return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::get(ctx->r, v) : StageDispatch<float>::get(ctx->r, v);
+}
+
+static size_t elem_size(const sbli_ctx* x);
+static int64_t npoints(const sbli_ctx* x);
+
+// Allocates the staged form's scratch once (kept until sbli_destroy).
+static hipError_t ensure_staged_scratch(sbli_ctx* x) {
+    if (x->stg) return hipSuccess;
+    return hipMalloc(&x->stg, (size_t)kStagedScratchWords * (size_t)npoints(x) * elem_size(x));
 }
 
 // Rebuilds the box's launch-table entry for the current variant and zchunk and
@@ -107,6 +126,7 @@ static StageVariant variant_of(const sbli_ctx* ctx, int v) {
 // copy so the host copy may change again.  The step time is 1 in the table;
 // each launch passes the actual dt as its scale.
 static hipError_t update_table(sbli_ctx* x) {
+    if (is_staged(x, x->variant)) return ensure_staged_scratch(x);   // no launch table
     const StageVariant v = variant_of(x, x->variant);
     if (x->p.dtype == SBLI_F64) {
         x->inst64.c = x->c64;
@@ -143,8 +163,8 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     if (!out) return fail(nullptr, SBLI_ERR_ARG, "sbli_init: out is NULL");
     *out = nullptr;
     if (!p) return fail(nullptr, SBLI_ERR_ARG, "sbli_init: params is NULL");
-    if (p->order != 2 && p->order != 4 && p->order != 6 && p->order != 8)
-        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: order must be 2, 4, 6 or 8 (got %d)", p->order);
+    if (p->order < 2 || p->order > 2 * kMaxR || p->order % 2 != 0)
+        return fail(nullptr, SBLI_ERR_ARG, "sbli_init: order must be even, 2 to %d (got %d)", 2 * kMaxR, p->order);
     const int nmin = 2 * p->order + 1;
     if (p->nx < nmin || p->ny < nmin || p->nz < nmin)
         return fail(nullptr, SBLI_ERR_ARG, "sbli_init: every grid size must be >= %d for order %d (got %d x %d x %d)",
@@ -198,6 +218,7 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
         hipFree(x->diag_da);
         hipFree(x->diag_out);
         hipFree(x->inst_dev);
+        hipFree(x->stg);
         delete x;
         return code;
     }
@@ -212,6 +233,7 @@ extern "C" int sbli_destroy(sbli_ctx* ctx) {
     hipFree(ctx->diag_da);
     hipFree(ctx->diag_out);
     hipFree(ctx->inst_dev);
+    hipFree(ctx->stg);
     hipFree(ctx->clos);
     hipFree(ctx->cflag);
     hipFree(ctx->ccount);
@@ -241,7 +263,19 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
     return SBLI_OK;
 }
 
+// Enqueues one residual / stage launch of the selected variant.  The staged
+// form's scratch exists whenever it is selected (update_table allocates it and
+// a failed allocation leaves the previous variant selected); it is checked
+// again here so that no launch ever runs without it.
 static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
+    if (is_staged(ctx, ctx->variant)) {
+        if (!ctx->stg) return;
+        const bool f64 = ctx->p.dtype == SBLI_F64;
+        const StagedArgs a{ctx->stream, f64, ctx->r, f64 ? (const void*)&ctx->c64 : (const void*)&ctx->c32,
+                           ctx->stg, mode, dt, A, B, ctx->net ? ctx->clos : nullptr, ctx->net ? ctx->cflag : nullptr};
+        staged_launch(a, qin, dq, qout);
+        return;
+    }
     const int sym = ctx->p.bc[0] | ctx->p.bc[1] | ctx->p.bc[2];
     const StageArgs a{ctx->stream, ctx->inst_dev, 1, total_wg(ctx), mode, dt, A, B, sym};
     if (ctx->p.dtype == SBLI_F64)
@@ -311,10 +345,12 @@ extern "C" int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]) {
                                                                      ctx->p.bc[2], ctx->diag_part)
     if (ctx->p.dtype == SBLI_F64) {
         if (r == 1) DIAG_LAUNCH(double, 1); else if (r == 2) DIAG_LAUNCH(double, 2);
-        else if (r == 3) DIAG_LAUNCH(double, 3); else DIAG_LAUNCH(double, 4);
+        else if (r == 3) DIAG_LAUNCH(double, 3); else if (r == 4) DIAG_LAUNCH(double, 4);
+        else if (r == 5) DIAG_LAUNCH(double, 5); else DIAG_LAUNCH(double, 6);
     } else {
         if (r == 1) DIAG_LAUNCH(float, 1); else if (r == 2) DIAG_LAUNCH(float, 2);
-        else if (r == 3) DIAG_LAUNCH(float, 3); else DIAG_LAUNCH(float, 4);
+        else if (r == 3) DIAG_LAUNCH(float, 3); else if (r == 4) DIAG_LAUNCH(float, 4);
+        else if (r == 5) DIAG_LAUNCH(float, 5); else DIAG_LAUNCH(float, 6);
     }
 #undef DIAG_LAUNCH
     HIP_TRY(ctx, hipGetLastError());
@@ -355,9 +391,17 @@ extern "C" int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk) {
         return fail(ctx, SBLI_ERR_ARG, "sbli_set_tuning: variant %d out of range [0, %d)", variant, num_variants(ctx));
     if (zchunk < 1 || zchunk > ctx->p.nz)
         return fail(ctx, SBLI_ERR_ARG, "sbli_set_tuning: zchunk %d out of range [1, %d]", zchunk, ctx->p.nz);
+    const int old_v = ctx->variant, old_z = ctx->zchunk;
     ctx->variant = variant;
     ctx->zchunk = zchunk;
-    HIP_TRY(ctx, update_table(ctx));
+    const hipError_t e = update_table(ctx);
+    if (e != hipSuccess) {
+        ctx->variant = old_v;
+        ctx->zchunk = old_z;
+        update_table(ctx);
+        return fail(ctx, e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP, "sbli_set_tuning: %s",
+                    hipGetErrorString(e));
+    }
     return SBLI_OK;
 }
 
@@ -388,10 +432,14 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
     float best = 1e30f;
     int bv = ctx->variant, bz = ctx->zchunk;
     for (int v = 0; v < num_variants(ctx); ++v) {
-        for (int ci = 0; ci < nc; ++ci) {
+        // the staged form has no z-chunks; it is skipped when its scratch cannot be allocated
+        for (int ci = 0; ci < (is_staged(ctx, v) ? 1 : nc); ++ci) {
             ctx->variant = v;
             ctx->zchunk = cands[ci];
-            update_table(ctx);
+            if (update_table(ctx) != hipSuccess) {
+                (void)hipGetLastError();
+                continue;
+            }
             enqueue_steps(ctx, q, q_tmp, dq, dt, 1);          // warm-up
             hipEventRecord(e0, ctx->stream);
             enqueue_steps(ctx, q, q_tmp, dq, dt, reps);
@@ -567,6 +615,9 @@ extern "C" int sbli_batch_init(const sbli_instance* inst, int count, int order, 
     if (!out) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: out is NULL");
     *out = nullptr;
     if (!inst || count < 1) return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: need count >= 1 instances");
+    // one launch covers all boxes: only the fused stage kernel (orders 2..8) takes a box table
+    if (order != 2 && order != 4 && order != 6 && order != 8)
+        return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: order must be 2, 4, 6 or 8 (got %d)", order);
     for (int i = 0; i < count; ++i)
         if (!(inst[i].dt > 0 && std::isfinite(inst[i].dt)))
             return bfail(nullptr, SBLI_ERR_ARG, "sbli_batch_init: instance %d: dt must be finite and > 0", i);

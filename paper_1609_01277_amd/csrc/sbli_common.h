@@ -6,7 +6,7 @@
 
 namespace sbli {
 
-constexpr int kMaxR = 4;   // largest supported stencil radius (order 8)
+constexpr int kMaxR = 6;   // largest supported stencil radius (order 12)
 
 // Constants of one periodic box, pre-scaled so the kernels never divide by the
 // grid spacing (paper Sec. "Code generation": rationals and reciprocals such as

@@ -1,0 +1,61 @@
+// Launches of the staged form of the stage kernel (kernels_staged.h) for every
+// element type, radius 1..6 and mode; compiled in a translation unit of its own.
+#include "kernels_staged.h"
+#include "staged.h"
+
+namespace sbli {
+
+template <typename T, int R>
+static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* w, T* nf) {
+    const BoxConst<T>& c = *(const BoxConst<T>*)a.box;
+    const int64_t P = c.P;
+    const int64_t want = (P + kStagedThreads - 1) / kStagedThreads;
+    const unsigned blocks = (unsigned)(want < 1048576 ? want : 1048576);   // grid-stride beyond this
+    staged_point_kernel<T><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, P, c.gm1, c.gM2);
+    staged_nested_kernel<T, R><<<blocks, kStagedThreads, 0, a.stream>>>(w, nf, c);
+    const T dt = (T)a.dt, A = (T)a.A, B = (T)a.B;
+    const T* clos = (const T*)a.clos;
+    switch (a.mode) {
+        case kModeRHS:
+            staged_stage_kernel<T, R, kModeRHS><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A,
+                                                                                         B, clos, a.cflag);
+            break;
+        case kModeStage1:
+            staged_stage_kernel<T, R, kModeStage1><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
+                                                                                            A, B, clos, a.cflag);
+            break;
+        case kModeStage2:
+            staged_stage_kernel<T, R, kModeStage2><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
+                                                                                            A, B, clos, a.cflag);
+            break;
+        default:
+            staged_stage_kernel<T, R, kModeStage3><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
+                                                                                            A, B, clos, a.cflag);
+            break;
+    }
+}
+
+template <typename T>
+static void staged_dispatch(const StagedArgs& a, const void* qin, void* dq, void* qout) {
+    const int64_t P = ((const BoxConst<T>*)a.box)->P;
+    T* w = (T*)a.scratch;
+    T* nf = w + 5 * P;
+    const T* qi = (const T*)qin;
+    T* d = (T*)dq;
+    T* qo = (T*)qout;
+    switch (a.r) {
+        case 1: staged_run<T, 1>(a, qi, d, qo, w, nf); break;
+        case 2: staged_run<T, 2>(a, qi, d, qo, w, nf); break;
+        case 3: staged_run<T, 3>(a, qi, d, qo, w, nf); break;
+        case 4: staged_run<T, 4>(a, qi, d, qo, w, nf); break;
+        case 5: staged_run<T, 5>(a, qi, d, qo, w, nf); break;
+        default: staged_run<T, 6>(a, qi, d, qo, w, nf); break;
+    }
+}
+
+void staged_launch(const StagedArgs& a, const void* qin, void* dq, void* qout) {
+    if (a.f64) staged_dispatch<double>(a, qin, dq, qout);
+    else staged_dispatch<float>(a, qin, dq, qout);
+}
+
+}  // namespace sbli
