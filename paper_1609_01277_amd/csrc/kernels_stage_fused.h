@@ -442,7 +442,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 T cd[5] = {0, 0, 0, 0, 0};
                 if (NLD > 0) {
     #pragma unroll
-                    for (int f = 0; f < 5; ++f) cd[f] = dq[f * P + idx];
+                    for (int f = 0; f < 5; ++f) cd[f] = __builtin_nontemporal_load(&dq[f * P + idx]);
                 }
                 auto ld = [&](int yy, int xx) {
                     PF<T> f;
@@ -492,6 +492,8 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                     ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
                 }
                 if (store) {
+                    // dq and the new state are streamed: nothing reads them again in
+                    // this launch, so they need not displace the state in L2
                     T Rv[5] = {Rr, R0, R1, R2, RE};
                     if (clos != nullptr && cflag[0] != 0) {
     #pragma unroll
@@ -501,12 +503,12 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     #pragma unroll
                     for (int f = 0; f < 5; ++f) {
                         if (MODE == kModeRHS) {
-                            out[f * P + idx] = Rv[f];
+                            __builtin_nontemporal_store(Rv[f], &out[f * P + idx]);
                         } else {
                             T dn = dt * Rv[f];
                             if (MODE != kModeStage1) dn = fmaT(A, cd[f], dn);
-                            if (MODE != kModeStage3) dq[f * P + idx] = dn;
-                            out[f * P + idx] = fmaT(B, dn, qv[f]);
+                            if (MODE != kModeStage3) __builtin_nontemporal_store(dn, &dq[f * P + idx]);
+                            __builtin_nontemporal_store(fmaT(B, dn, qv[f]), &out[f * P + idx]);
                         }
                     }
                 } else {
