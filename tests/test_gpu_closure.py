@@ -219,3 +219,33 @@ def test_closure_fallback_when_guard_rejects_or_detached():
     q_det = s.tgv_init(s.empty_state())
     s.rk3_step(q_det, s.empty_state(), s.empty_state(), dt, 2)
     assert torch.equal(q_plain, q_det)
+
+
+def test_closure_term_same_in_staged_form():
+    """With a network attached, the staged form of the stage kernel adds the same closure
+    term as the fused variants: bitwise equal states after RK3 steps."""
+    sbli, closure, torch = _mods()
+    n, dt = 32, 3.385e-3
+    net = closure.ClosureNet(n, 1)
+    net.set_params(closure.join_params(nn.init_params(np.random.default_rng(4))).astype(np.float32) * 0.05)
+    stats = np.zeros(35, dtype=np.float32)
+    stats[5:10] = 1.0
+    stats[15:20] = 1.0
+    stats[20:25] = 1e3            # generous limits: every evaluation accepted
+    net.set_stats(stats)
+    s = sbli.Solver(n, order=4, dtype="f32", **synth.TGV)
+    closure.attach(s, net)
+    staged = len(s.variants()) - 1
+    out = []
+    for v in (0, staged):
+        s.set_tuning(v, n)
+        q = s.tgv_init(s.empty_state())
+        s.rk3_step(q, s.empty_state(), s.empty_state(), dt, 2)
+        out.append(q.cpu().numpy())
+    accepted, rejected = closure.counts(s)
+    assert accepted == 12 and rejected == 0
+    assert np.array_equal(out[0], out[1])
+    plain = sbli.Solver(n, order=4, dtype="f32", **synth.TGV)
+    qp = plain.tgv_init(plain.empty_state())
+    plain.rk3_step(qp, plain.empty_state(), plain.empty_state(), dt, 2)
+    assert not np.array_equal(out[0], qp.cpu().numpy())   # the term is not zero
