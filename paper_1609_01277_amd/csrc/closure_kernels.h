@@ -246,14 +246,30 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
 //   sd[o][32]                       dout of the block
 //   si[tap][c][32]                  input shifted by each of the 27 taps
 // then each wave accumulates its share of the Kpad32/32 column tiles.
+// A staging thread loads 8 channels of 10 consecutive points of one (dz, dy)
+// row (ten 16-byte loads: 8 points and one on each side), and for each of the
+// three x-shifts transposes an 8 x 8 block in registers and stores 8 points of
+// one channel per 16-byte LDS store; each input element is loaded once per
+// (dz, dy) instead of once per tap.  LDS rows are padded to 40 elements (80 bytes)
+// so that rows 8 or 32 apart, and the 32 rows one MFMA operand read spans, do
+// not fall on the same banks.
 // Results: per-workgroup partial sums part[wg][32][Kpad32] (FP32).
 constexpr int kWgradMaxTiles = 28;   // Kpad32 / 32 <= 28 (27 * 32 = 864)
+constexpr int kWgradRow = 40;        // LDS row length (elements) of sd and si
+
+// o[j][k] = r[k][j]: the 8 x 8 block of 16-bit elements transposed.
+__device__ __forceinline__ void transpose8x8(const bf16x8 (&r)[8], bf16x8 (&o)[8]) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) o[j][k] = r[k][j];
+}
 
 __global__ void __launch_bounds__(256) conv_wgrad_kernel(const __bf16* __restrict__ in, int cpad,
                                                          const __bf16* __restrict__ dout, int opad, int n,
                                                          int64_t nblocks, int Kpad32, float* __restrict__ part) {
-    __shared__ __attribute__((aligned(16))) __bf16 sd[32][32];
-    __shared__ __attribute__((aligned(16))) __bf16 si[27 * 32][32];   // [(tap * cpad + c)][point]
+    __shared__ __attribute__((aligned(16))) __bf16 sd[32][kWgradRow];
+    __shared__ __attribute__((aligned(16))) __bf16 si[27 * 32][kWgradRow];   // [(tap * cpad + c)][point]
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int row = lane & 31, half = lane >> 5;
@@ -276,26 +292,45 @@ __global__ void __launch_bounds__(256) conv_wgrad_kernel(const __bf16* __restric
         const int64_t b = r / ((int64_t)n * n);
         const int x0 = xb * 32;
         __syncthreads();   // previous block's LDS reads are done
-        // stage dout: 32 points x opad channels (opad / 8 loads of 8 channels per point)
-        for (int t = threadIdx.x; t < 32 * (opad / 8); t += blockDim.x) {
-            const int pt = t % 32, cg = t / 32;
-            const int64_t g = b * P + ((int64_t)z * n + y) * n + x0 + pt;
-            const bf16x8 v = *(const bf16x8*)(dout + g * opad + cg * 8);
+        // stage dout: 32 points x opad channels, 8 points x 8 channels per thread
+        for (int t = threadIdx.x; t < 4 * (opad / 8); t += blockDim.x) {
+            const int pg = t % 4, cg = t / 4;
+            const int64_t g = b * P + ((int64_t)z * n + y) * n + x0 + pg * 8;
+            bf16x8 r[8], o[8];
 #pragma unroll
-            for (int j = 0; j < 8; ++j) sd[cg * 8 + j][pt] = v[j];
+            for (int k = 0; k < 8; ++k) r[k] = *(const bf16x8*)(dout + (g + k) * opad + cg * 8);
+            transpose8x8(r, o);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) *(bf16x8*)(&sd[cg * 8 + j][pg * 8]) = o[j];
         }
-        for (int t = threadIdx.x + opad * 32; t < 32 * 32; t += blockDim.x) sd[t / 32][t % 32] = (__bf16)0.0f;
-        // stage the input for every tap
-        for (int t = threadIdx.x; t < 27 * 32 * (cpad / 8); t += blockDim.x) {
-            const int pt = t % 32;
-            const int rest = t / 32;
-            const int cg = rest % (cpad / 8);
-            const int tap = rest / (cpad / 8);
-            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-            const int64_t g = b * P + ((int64_t)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n + wrapn(x0 + pt + dx, n);
-            const bf16x8 v = *(const bf16x8*)(in + g * cpad + cg * 8);
+        for (int t = threadIdx.x; t < (32 - opad) * 4; t += blockDim.x) {
+            bf16x8 zero;
 #pragma unroll
-            for (int j = 0; j < 8; ++j) si[tap * cpad + cg * 8 + j][pt] = v[j];
+            for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
+            *(bf16x8*)(&sd[opad + t / 4][(t % 4) * 8]) = zero;
+        }
+        // stage the input for every tap: one (dz, dy) row segment per thread item
+        for (int t = threadIdx.x; t < 9 * 4 * (cpad / 8); t += blockDim.x) {
+            const int pg = t % 4;
+            const int rest = t / 4;
+            const int cg = rest % (cpad / 8);
+            const int zy = rest / (cpad / 8);              // (dz + 1) * 3 + (dy + 1)
+            const int dz = zy / 3 - 1, dy = zy % 3 - 1;
+            const int64_t row = b * P + ((int64_t)wrapn(z + dz, n) * n + wrapn(y + dy, n)) * n;
+            bf16x8 r[10];
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+                r[k] = *(const bf16x8*)(in + (row + wrapn(x0 + pg * 8 + k - 1, n)) * cpad + cg * 8);
+#pragma unroll
+            for (int sx = 0; sx < 3; ++sx) {                // dx = sx - 1
+                const int tap = zy * 3 + sx;
+                bf16x8 blk[8], o[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) blk[k] = r[k + sx];
+                transpose8x8(blk, o);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) *(bf16x8*)(&si[tap * cpad + cg * 8 + j][pg * 8]) = o[j];
+            }
         }
         __syncthreads();
         // A[o][pts] from sd, B[pts][kk] from si; two k-steps of 16 points
