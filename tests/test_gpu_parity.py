@@ -166,14 +166,17 @@ FULL = [(256, 4), (256, 8), (512, 4), (512, 8)]
 @pytest.mark.parametrize("n,order", FULL)
 def test_full_size_sampled_step_parity(oracle_mod, n, order):
     """Full-size Taylor-Green (256^3, 512^3; orders 4, 8), FP64, one RK3 step with the
-    paper's dt, through the same entry point the benchmark times; sampled points are
-    computed one by one by the oracle.  Conservation sums must not drift."""
+    paper's dt, through the same entry point and in the same autotuned launch
+    configuration the benchmark times; sampled points are computed one by one by the
+    oracle.  Conservation sums must not drift."""
     sbli, torch = _sbli()
     dt = synth.tgv_dt(n)
     p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
     print("building oracle TGV state %d^3" % n, flush=True)
     q0 = oracle.tgv_init(p)
     s = sbli.Solver(n, order=order, **synth.TGV)
+    tune = s.autotune(reps=2)
+    print("launch configuration", tune, flush=True)
     q = to_dev(torch, q0)
     qt, dq = s.empty_state(), s.empty_state()
     d0, _ = s.diagnostics(q)
