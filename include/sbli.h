@@ -153,7 +153,8 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *   rotation (1) or shifting (0), wavefronts per SIMD its register allocation
  *   allows at least (1: as many registers as the kernel wants), barrier
  *   schedule (0: two barriers per z-plane; 1: double-buffered LDS planes, one
- *   barrier)} of a variant (6 ints written); all six are 0 for the staged form.
+ *   barrier, where the R planes below the output plane are kept (0: registers,
+ *   1: LDS)} of a variant (7 ints written); all seven are 0 for the staged form.
  * sbli_set_tuning / sbli_get_tuning: select / read the variant and zchunk used
  *   by sbli_rhs and sbli_rk3_step (1 <= zchunk <= nz; the staged form ignores
  *   zchunk).  sbli_set_tuning waits for the context's stream (it updates a small
@@ -166,7 +167,7 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *   unspecified (they are advanced in time).  Synchronises the stream.
  */
 int sbli_num_variants(const sbli_ctx* ctx);
-int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[6]);
+int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[7]);
 int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk);
 int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk);
 int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms);

@@ -138,7 +138,7 @@ def sbli_num_variants(ctx):
 
 
 def sbli_variant_info(ctx, variant):
-    info = (ctypes.c_int * 6)()
+    info = (ctypes.c_int * 7)()
     _check(load().sbli_variant_info(ctx, int(variant), info), ctx)
     return tuple(info)
 

@@ -206,7 +206,7 @@ struct DirSums {
 // planes).
 // clos (may be null): a closure term with the state's planar layout, added to
 // the residual when *cflag != 0.
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int SYM, int DB>
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int SYM, int DB, int ZL>
 __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                                                  const BoxConst<T>& c, int x0, int y0, int z0, int zc, T dt, T A,
                                                  T B, const T* __restrict__ clos, const int* __restrict__ cflag) {
@@ -219,6 +219,10 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     // and (V_z, Th_z) of the last 2R+1 gradient planes over the tile.
     __shared__ T s_axy[R + 1][4][S::BY1][S::BX1];
     __shared__ T s_az[2 * R + 1][2][TY][TX];
+    // ZL: the point fields of the R planes below the output plane (own column,
+    // stored when a plane leaves the centre of the window) are kept in LDS
+    // instead of the register window, which then needs 2R + 1 live planes.
+    __shared__ T s_zt[ZL ? R : 1][ZL ? kPlFields : 1][ZL ? TY : 1][ZL ? TX : 1];
 
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P;
@@ -460,6 +464,25 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 };
                 const PF<T>& s = Qb[slot(R)];
                 auto& axy = s_axy[(it - R) % (R + 1)];   // nested fields of plane o
+                auto below = [&](int m) -> PF<T> {         // point fields of plane o - m
+                    if constexpr (ZL) {
+                        const int k = (it - m) % R;
+                        PF<T> f;
+                        f.rho = s_zt[k][0][cy][cx];
+                        f.m0 = s_zt[k][1][cy][cx];
+                        f.m1 = s_zt[k][2][cy][cx];
+                        f.m2 = s_zt[k][3][cy][cx];
+                        f.E = s_zt[k][4][cy][cx];
+                        f.u0 = s_zt[k][5][cy][cx];
+                        f.u1 = s_zt[k][6][cy][cx];
+                        f.u2 = s_zt[k][7][cy][cx];
+                        f.p = s_zt[k][8][cy][cx];
+                        f.Tm = s_zt[k][9][cy][cx];
+                        return f;
+                    } else {
+                        return Qb[slot(R - m)];
+                    }
+                };
                 T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
                 {
                     DirSums<T> ds;
@@ -485,7 +508,7 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
     #pragma unroll
                     for (int m = 1; m <= R; ++m)
                         ds.template add<2>(Qb[slot(R + m)], s_az[(it + m - R) % (2 * R + 1)][0][cy][cx],
-                                           s_az[(it + m - R) % (2 * R + 1)][1][cy][cx], Qb[slot(R - m)],
+                                           s_az[(it + m - R) % (2 * R + 1)][1][cy][cx], below(m),
                                            s_az[(it - m - R) % (2 * R + 1)][0][cy][cx],
                                            s_az[(it - m - R) % (2 * R + 1)][1][cy][cx],
                                            c.da[2][m - 1], c.d2c[2][m - 1]);
@@ -516,6 +539,24 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 }
             } else {
                 dropped_stores<NLD + NST>(out);
+            }
+            if constexpr (ZL) {
+                // plane o leaves the centre of the window; only this thread reads it
+                // back, as plane o' - m of the next R output planes
+                if (interior && it >= 2 * R) {
+                    const PF<T>& f = Qb[slot(R)];
+                    const int k = it % R;
+                    s_zt[k][0][cy][cx] = f.rho;
+                    s_zt[k][1][cy][cx] = f.m0;
+                    s_zt[k][2][cy][cx] = f.m1;
+                    s_zt[k][3][cy][cx] = f.m2;
+                    s_zt[k][4][cy][cx] = f.E;
+                    s_zt[k][5][cy][cx] = f.u0;
+                    s_zt[k][6][cy][cx] = f.u1;
+                    s_zt[k][7][cy][cx] = f.u2;
+                    s_zt[k][8][cy][cx] = f.p;
+                    s_zt[k][9][cy][cx] = f.Tm;
+                }
             }
             __builtin_amdgcn_sched_barrier(0);
     };
@@ -553,8 +594,8 @@ struct BoxInst {
 // MINW: the fewest wavefronts per SIMD the register allocation must allow
 // (2 caps a thread at 256 VGPRs, so two 4-wavefront workgroups share a CU).
 // SYM: 1 for boxes with a symmetry axis, 0 for periodic boxes.
-// DB: barrier schedule (see fused_stage_body).
-template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW, int SYM, int DB>
+// DB: barrier schedule; ZL: lower planes of the window in LDS (see fused_stage_body).
+template <typename T, int R, int TX, int TY, int MODE, int PRE, int RT, int MINW, int SYM, int DB, int ZL>
 __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     fused_stage_kernel(const T* __restrict__ q, T* __restrict__ dq, T* __restrict__ out,
                        const BoxInst<T>* __restrict__ inst, int ninst, T dt_scale, T A, T B) {
@@ -576,7 +617,7 @@ __global__ void __launch_bounds__((FusedShape<R, TX, TY>::NT), MINW)
     const int z0 = chunk * b.zchunk;
     const int zc = min(b.zchunk, b.c.n[2] - z0);
     T* dqb = dq ? dq + b.offset : nullptr;
-    fused_stage_body<T, R, TX, TY, MODE, PRE, RT, SYM, DB>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
+    fused_stage_body<T, R, TX, TY, MODE, PRE, RT, SYM, DB, ZL>(q + b.offset, dqb, out + b.offset, b.c, tx * TX, ty * TY, z0, zc,
                                               b.dt * dt_scale, A, B, b.closure, b.cflag);
 }
 

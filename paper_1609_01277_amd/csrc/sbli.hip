@@ -108,7 +108,7 @@ static int num_variants(const sbli_ctx* ctx) { return num_fused(ctx) + 1; }
 static bool is_staged(const sbli_ctx* ctx, int v) { return v == num_fused(ctx); }
 
 static StageVariant variant_of(const sbli_ctx* ctx, int v) {
-    if (is_staged(ctx, v)) return StageVariant{0, 0, 0, 0, 0, 0};
+    if (is_staged(ctx, v)) return StageVariant{0, 0, 0, 0, 0, 0, 0};
     return ctx->p.dtype == SBLI_F64 ? StageDispatch<double>::get(ctx->r, v) : StageDispatch<float>::get(ctx->r, v);
 }
 
@@ -371,7 +371,7 @@ extern "C" int sbli_num_variants(const sbli_ctx* ctx) {
     return num_variants(ctx);
 }
 
-extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[6]) {
+extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[7]) {
     if (!ctx || !info) return fail(nullptr, SBLI_ERR_ARG, "sbli_variant_info: NULL argument");
     if (variant < 0 || variant >= num_variants(ctx))
         return fail(const_cast<sbli_ctx*>(ctx), SBLI_ERR_ARG, "sbli_variant_info: variant %d out of range", variant);
@@ -382,6 +382,7 @@ extern "C" int sbli_variant_info(const sbli_ctx* ctx, int variant, int info[6]) 
     info[3] = v.rot;
     info[4] = v.minw;
     info[5] = v.db;
+    info[6] = v.zl;
     return SBLI_OK;
 }
 

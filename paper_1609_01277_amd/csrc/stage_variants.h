@@ -14,24 +14,26 @@ struct StageVariant {
     int tx, ty, pre, rot;
     int minw;   // wavefronts per SIMD the register allocation must allow (1 = as many VGPRs as needed)
     int db;     // 1: double-buffered LDS planes, one barrier per z-iteration
+    int zl;     // 1: the R planes below the output plane in LDS instead of registers
 };
 
-// X-macro lists of (TX, TY, PRE, RT, MINW, DB) per (type, radius).  The first
+// X-macro lists of (TX, TY, PRE, RT, MINW, DB, ZL) per (type, radius).  The first
 // entry is the default before tuning.
 #define SBLI_VARIANTS_D1(X) \
-    X(16, 16, 1, 0, 1, 0) X(16, 16, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 0) X(16, 8, 1, 1, 2, 0) X(16, 16, 1, 1, 1, 1)
+    X(16, 16, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 1, 0, 0) X(16, 8, 1, 1, 2, 0, 0) X(16, 16, 1, 1, 1, 1, 0)
 #define SBLI_VARIANTS_D2(X)                                                                                    \
-    X(16, 16, 1, 0, 1, 0) X(16, 16, 1, 1, 1, 0) X(16, 16, 0, 1, 1, 0) X(32, 8, 0, 0, 1, 0) X(16, 8, 1, 1, 2, 0) \
-    X(16, 16, 1, 1, 1, 1) X(16, 16, 1, 0, 1, 1)
-#define SBLI_VARIANTS_D3(X) X(8, 8, 0, 0, 1, 0) X(8, 8, 1, 0, 1, 0) X(16, 8, 1, 0, 1, 0) X(16, 8, 1, 0, 1, 1)
-#define SBLI_VARIANTS_D4(X) X(16, 4, 0, 0, 1, 0) X(16, 4, 1, 0, 1, 0) X(8, 8, 0, 0, 1, 0)
+    X(16, 16, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(16, 16, 0, 1, 1, 0, 0) X(32, 8, 0, 0, 1, 0, 0) X(16, 8, 1, 1, 2, 0, 0) \
+    X(16, 16, 1, 1, 1, 1, 0) X(16, 16, 1, 0, 1, 1, 0)
+#define SBLI_VARIANTS_D3(X) X(8, 8, 0, 0, 1, 0, 0) X(8, 8, 1, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 1, 0)
+#define SBLI_VARIANTS_D4(X) \
+    X(16, 4, 0, 0, 1, 0, 0) X(16, 4, 1, 0, 1, 0, 0) X(8, 8, 0, 0, 1, 0, 0) X(16, 4, 1, 0, 1, 0, 1) X(8, 8, 1, 0, 1, 0, 1)
 #define SBLI_VARIANTS_F1(X) \
-    X(16, 16, 1, 0, 1, 0) X(16, 16, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 0) X(16, 8, 1, 0, 1, 0) X(16, 16, 1, 1, 1, 1)
+    X(16, 16, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 1, 0)
 #define SBLI_VARIANTS_F2(X)                                                                                   \
-    X(16, 8, 1, 0, 1, 0) X(16, 8, 1, 1, 1, 0) X(16, 16, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 0) X(32, 8, 1, 1, 3, 0) \
-    X(16, 16, 1, 1, 3, 0) X(16, 16, 1, 1, 1, 1) X(32, 8, 1, 1, 1, 1) X(16, 16, 1, 1, 3, 1)
-#define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0, 1, 0) X(16, 16, 1, 0, 1, 0) X(16, 8, 1, 0, 1, 0)
-#define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0, 1, 0) X(16, 8, 1, 0, 1, 0) X(16, 4, 1, 0, 1, 0)
+    X(16, 8, 1, 0, 1, 0, 0) X(16, 8, 1, 1, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 3, 0, 0) \
+    X(16, 16, 1, 1, 3, 0, 0) X(16, 16, 1, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 1, 0) X(16, 16, 1, 1, 3, 1, 0)
+#define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0, 1, 0, 0) X(16, 16, 1, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0)
+#define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0) X(16, 4, 1, 0, 1, 0, 0)
 
 // One launch: the boxes (device table), their total workgroup count, the mode
 // and the RK coefficients.
@@ -45,33 +47,33 @@ struct StageArgs {
     int sym;            // 1 if a box of the launch has a symmetry axis
 };
 
-template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int DB, int MODE>
+template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int DB, int ZL, int MODE>
 inline void launch_fused_cfg(const StageArgs& a, const T* qin, T* dq, T* qout) {
     if (a.sym)
-        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 1, DB><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT,
+        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 1, DB, ZL><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT,
                                                                        0, a.stream>>>(
             qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
     else
-        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 0, DB><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT,
+        fused_stage_kernel<T, R, TX, TY, MODE, PRE, RT, MINW, 0, DB, ZL><<<dim3(a.total_wg), FusedShape<R, TX, TY>::NT,
                                                                        0, a.stream>>>(
             qin, dq, qout, (const BoxInst<T>*)a.inst, a.ninst, (T)a.dt_scale, (T)a.A, (T)a.B);
 }
 
-template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int DB>
+template <typename T, int R, int TX, int TY, int PRE, int RT, int MINW, int DB, int ZL>
 inline bool try_variant(int& k, int want, const StageArgs& a, const T* qin, T* dq, T* qout) {
     if (k++ != want) return false;
     switch (a.mode) {
-        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, kModeRHS>(a, qin, dq, qout); break;
-        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, kModeStage1>(a, qin, dq, qout); break;
-        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, kModeStage2>(a, qin, dq, qout); break;
-        default: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, kModeStage3>(a, qin, dq, qout); break;
+        case kModeRHS: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, ZL, kModeRHS>(a, qin, dq, qout); break;
+        case kModeStage1: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, ZL, kModeStage1>(a, qin, dq, qout); break;
+        case kModeStage2: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, ZL, kModeStage2>(a, qin, dq, qout); break;
+        default: launch_fused_cfg<T, R, TX, TY, PRE, RT, MINW, DB, ZL, kModeStage3>(a, qin, dq, qout); break;
     }
     return true;
 }
 
-#define SBLI_TRY(TX_, TY_, PRE_, RT_, MINW_, DB_) \
-    if (try_variant<T, R, TX_, TY_, PRE_, RT_, MINW_, DB_>(k, v, a, qin, dq, qout)) return true;
-#define SBLI_ENTRY(TX_, TY_, PRE_, RT_, MINW_, DB_) StageVariant{TX_, TY_, PRE_, RT_, MINW_, DB_},
+#define SBLI_TRY(TX_, TY_, PRE_, RT_, MINW_, DB_, ZL_) \
+    if (try_variant<T, R, TX_, TY_, PRE_, RT_, MINW_, DB_, ZL_>(k, v, a, qin, dq, qout)) return true;
+#define SBLI_ENTRY(TX_, TY_, PRE_, RT_, MINW_, DB_, ZL_) StageVariant{TX_, TY_, PRE_, RT_, MINW_, DB_, ZL_},
 
 template <typename T, int R>
 struct VariantSet;

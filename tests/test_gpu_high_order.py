@@ -43,7 +43,7 @@ def test_high_order_rhs_matches_oracle(order):
     n = (26, 27, 29)
     q0 = synth.random_conservative_state(n, seed=40 + order, mom=0.3)
     s = sbli.Solver(n, order=order, **synth.TGV)
-    assert s.variants() == [(0, 0, 0, 0, 0, 0)]      # the staged form only
+    assert s.variants() == [(0, 0, 0, 0, 0, 0, 0)]      # the staged form only
     R = s.rhs(torch.from_numpy(q0).cuda()).cpu().numpy()
     errs = rel_err(R, oracle.rhs(q0, oracle.Params(n=n, order=order, **synth.TGV)))
     assert max(errs) <= TOL64, errs
@@ -96,7 +96,7 @@ def test_staged_form_bitwise_equals_fused(dtype, bc, order):
     s = sbli.Solver(n, order=order, dtype=dtype, Re=80.0, Mach=0.3, length=length, bc=bc)
     variants = s.variants()
     staged = len(variants) - 1
-    assert variants[staged] == (0, 0, 0, 0, 0, 0)
+    assert variants[staged] == (0, 0, 0, 0, 0, 0, 0)
     out = {}
     for v in (0, staged):
         s.set_tuning(v, n[2])
