@@ -6,10 +6,10 @@
 // order (make_pf, the gradient sums, DirSums::add / finish, the 2N update).
 //
 //   1. staged_point_kernel:  w = (u_0, u_1, u_2, p, T) of every point;
-//   2. staged_nested_kernel: nf = (V_0, V_1, V_2, theta - g_00, theta - g_11,
-//      theta - g_22) with g_ij = D_j u_i, V_j = u_i tau_ij (paper Sec.
-//      "Expanding": the inner derivative of a nested term is taken first);
-//   3. staged_stage_kernel:  the residual (paper eqs. of mass, momentum and
+//   2. staged_nested_tiled_kernel: nf = (V_0, V_1, V_2, theta - g_00,
+//      theta - g_11, theta - g_22) with g_ij = D_j u_i, V_j = u_i tau_ij (paper
+//      Sec. "Expanding": the inner derivative of a nested term is taken first);
+//   3. staged_tiled_kernel:  the residual (paper eqs. of mass, momentum and
 //      energy in the skew-symmetric form) from q, w and nf at the 2R
 //      neighbours along each axis, then the 2N Runge-Kutta update.
 //
@@ -23,14 +23,6 @@
 namespace sbli {
 
 constexpr int kStagedThreads = 256;
-
-// Linear index of the neighbour m points away along an axis (coordinate c,
-// stride `stride`, n points, sym = mirrored ends); `flip` gets the sign mask.
-__device__ __forceinline__ int64_t staged_nb(int64_t id, int c, int m, int n, int64_t stride, int sym,
-                                             unsigned& flip) {
-    const int cc = map_index(c + m, n, sym, flip);
-    return id + (int64_t)(cc - c) * stride;
-}
 
 template <typename T>
 __global__ void __launch_bounds__(kStagedThreads)
@@ -46,38 +38,196 @@ __global__ void __launch_bounds__(kStagedThreads)
     }
 }
 
-template <typename T, int R>
-__global__ void __launch_bounds__(kStagedThreads)
-    staged_nested_kernel(const T* __restrict__ w, T* __restrict__ nf, const BoxConst<T> c) {
+// Steps 2 and 3 run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
+// (x, y) columns and a run of z-planes.  Per plane it stages what the x/y
+// stencils read, over the tile and an R-wide ring (corners excluded), into LDS,
+// so every element is loaded once instead of once per neighbour that needs it;
+// the z neighbours of the thread's own column come from memory.
+//
+// The residual step: point fields and the x/y nested fields staged.
+constexpr int kStagedTile = 16;
+constexpr int kStagedFields = 14;   // rho, rho u_i, rho E, u_i, p, T, V_x, Th_x, V_y, Th_y
+
+template <typename T, int R, int MODE>
+__global__ void __launch_bounds__(kStagedTile * kStagedTile)
+    staged_tiled_kernel(const T* __restrict__ q, const T* __restrict__ w, const T* __restrict__ nf,
+                        T* __restrict__ dq, T* __restrict__ out, const BoxConst<T> c, T dt, T A, T B,
+                        const T* __restrict__ clos, const int* __restrict__ cflag, int tiles_x, int tiles_y,
+                        int zchunk) {
+    constexpr int TS = kStagedTile, BW = TS + 2 * R;
+    __shared__ T sb[kStagedFields][BW][BW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
-    const int64_t P = c.P, sy = nx, sz = (int64_t)nx * ny;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < P; id += stride) {
-        const int i = (int)(id % nx);
-        const int64_t t = id / nx;
-        const int j = (int)(t % ny);
-        const int k = (int)(t / ny);
+    const int64_t P = c.P, plane = (int64_t)nx * ny;
+    const int tile = blockIdx.x % (tiles_x * tiles_y);
+    const int z0 = (blockIdx.x / (tiles_x * tiles_y)) * zchunk;
+    const int z1 = min(z0 + zchunk, nz);
+    const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
+    const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;
+    const bool store = x0 + cx < nx && y0 + cy < ny;
+    unsigned fdummy;
+    // own column (folded for lanes of a ragged tile; their results are not stored)
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fdummy) * nx + fold_index(x0 + cx, nx, c.sym[0], fdummy);
+    auto point_at = [&](int64_t ix) {
+        PF<T> p;
+        p.rho = q[ix];
+        p.m0 = q[P + ix];
+        p.m1 = q[2 * P + ix];
+        p.m2 = q[3 * P + ix];
+        p.E = q[4 * P + ix];
+        p.u0 = w[ix];
+        p.u1 = w[P + ix];
+        p.u2 = w[2 * P + ix];
+        p.p = w[3 * P + ix];
+        p.Tm = w[4 * P + ix];
+        return p;
+    };
+    auto lds_point = [&](int ly, int lx) {
+        PF<T> p;
+        p.rho = sb[0][ly][lx];
+        p.m0 = sb[1][ly][lx];
+        p.m1 = sb[2][ly][lx];
+        p.m2 = sb[3][ly][lx];
+        p.E = sb[4][ly][lx];
+        p.u0 = sb[5][ly][lx];
+        p.u1 = sb[6][ly][lx];
+        p.u2 = sb[7][ly][lx];
+        p.p = sb[8][ly][lx];
+        p.Tm = sb[9][ly][lx];
+        return p;
+    };
+    for (int z = z0; z < z1; ++z) {
+        const int64_t pz = (int64_t)z * plane;
+        __syncthreads();   // the previous plane's LDS reads are done
+        for (int e = tid; e < BW * BW; e += TS * TS) {
+            const int lx = e % BW, ly = e / BW;
+            // the four R x R corners are never read
+            if ((lx < R || lx >= R + TS) && (ly < R || ly >= R + TS)) continue;
+            unsigned fx, fy;
+            const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
+                               fold_index(x0 - R + lx, nx, c.sym[0], fx);
+            const PF<T> p = point_at(ix);
+            sb[0][ly][lx] = p.rho;
+            sb[1][ly][lx] = flip_sign(p.m0, fx);
+            sb[2][ly][lx] = flip_sign(p.m1, fy);
+            sb[3][ly][lx] = p.m2;
+            sb[4][ly][lx] = p.E;
+            sb[5][ly][lx] = flip_sign(p.u0, fx);
+            sb[6][ly][lx] = flip_sign(p.u1, fy);
+            sb[7][ly][lx] = p.u2;
+            sb[8][ly][lx] = p.p;
+            sb[9][ly][lx] = p.Tm;
+            sb[10][ly][lx] = flip_sign(nf[ix], fx);            // V_x: odd under an x mirror
+            sb[11][ly][lx] = nf[3 * P + ix];                    // theta - g_xx
+            sb[12][ly][lx] = flip_sign(nf[P + ix], fy);         // V_y
+            sb[13][ly][lx] = nf[4 * P + ix];                    // theta - g_yy
+        }
+        __syncthreads();
+        const int ly = R + cy, lx = R + cx;
+        const PF<T> s = lds_point(ly, lx);
+        T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
+        {
+            DirSums<T> ds;
+            ds.zero();
+#pragma unroll 1
+            for (int m = 1; m <= R; ++m)
+                ds.template add<0>(lds_point(ly, lx + m), sb[10][ly][lx + m], sb[11][ly][lx + m], lds_point(ly, lx - m),
+                                   sb[10][ly][lx - m], sb[11][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
+            ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
+        }
+        {
+            DirSums<T> ds;
+            ds.zero();
+#pragma unroll 1
+            for (int m = 1; m <= R; ++m)
+                ds.template add<1>(lds_point(ly + m, lx), sb[12][ly + m][lx], sb[13][ly + m][lx], lds_point(ly - m, lx),
+                                   sb[12][ly - m][lx], sb[13][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
+            ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
+        }
+        {
+            DirSums<T> ds;
+            ds.zero();
+#pragma unroll 1
+            for (int m = 1; m <= R; ++m) {
+                unsigned fa, fb;
+                const int64_t ia = (int64_t)map_index(z + m, nz, c.sym[2], fa) * plane + col;
+                const int64_t ib = (int64_t)map_index(z - m, nz, c.sym[2], fb) * plane + col;
+                PF<T> a = point_at(ia), b = point_at(ib);
+                a.m2 = flip_sign(a.m2, fa);
+                a.u2 = flip_sign(a.u2, fa);
+                b.m2 = flip_sign(b.m2, fb);
+                b.u2 = flip_sign(b.u2, fb);
+                ds.template add<2>(a, flip_sign(nf[2 * P + ia], fa), nf[5 * P + ia], b, flip_sign(nf[2 * P + ib], fb),
+                                   nf[5 * P + ib], c.da[2][m - 1], c.d2c[2][m - 1]);
+            }
+            ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
+        }
+        if (store) {
+            const int64_t id = pz + col;
+            T Rv[5] = {Rr, R0, R1, R2, RE};
+            if (clos != nullptr && cflag[0] != 0) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) Rv[f] += clos[f * P + id];
+            }
+            const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
+#pragma unroll
+            for (int f = 0; f < 5; ++f) {
+                if (MODE == kModeRHS) {
+                    out[f * P + id] = Rv[f];
+                } else {
+                    T dn = dt * Rv[f];
+                    if (MODE != kModeStage1) dn = fmaT(A, dq[f * P + id], dn);
+                    if (MODE != kModeStage3) dq[f * P + id] = dn;
+                    out[f * P + id] = fmaT(B, dn, qv[f]);
+                }
+            }
+        }
+    }
+}
+
+// The nested-field step: the velocity staged.
+template <typename T, int R>
+__global__ void __launch_bounds__(kStagedTile * kStagedTile)
+    staged_nested_tiled_kernel(const T* __restrict__ w, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
+                               int tiles_y, int zchunk) {
+    constexpr int TS = kStagedTile, BW = TS + 2 * R;
+    __shared__ T su[3][BW][BW];
+    const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
+    const int64_t P = c.P, plane = (int64_t)nx * ny;
+    const int tile = blockIdx.x % (tiles_x * tiles_y);
+    const int z0 = (blockIdx.x / (tiles_x * tiles_y)) * zchunk;
+    const int z1 = min(z0 + zchunk, nz);
+    const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
+    const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;
+    const bool store = x0 + cx < nx && y0 + cy < ny;
+    unsigned fdummy;
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fdummy) * nx + fold_index(x0 + cx, nx, c.sym[0], fdummy);
+    for (int z = z0; z < z1; ++z) {
+        const int64_t pz = (int64_t)z * plane;
+        __syncthreads();
+        for (int e = tid; e < BW * BW; e += TS * TS) {
+            const int lx = e % BW, ly = e / BW;
+            if ((lx < R || lx >= R + TS) && (ly < R || ly >= R + TS)) continue;
+            unsigned fx, fy;
+            const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
+                               fold_index(x0 - R + lx, nx, c.sym[0], fx);
+            su[0][ly][lx] = flip_sign(w[ix], fx);
+            su[1][ly][lx] = flip_sign(w[P + ix], fy);
+            su[2][ly][lx] = w[2 * P + ix];
+        }
+        __syncthreads();
+        const int ly = R + cy, lx = R + cx;
         T g[3][3];
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
             T sx = 0, syy = 0, szz = 0;
 #pragma unroll
             for (int m = 1; m <= R; ++m) {
+                sx = fmaT(c.da[0][m - 1], su[b][ly][lx + m] - su[b][ly][lx - m], sx);
+                syy = fmaT(c.da[1][m - 1], su[b][ly + m][lx] - su[b][ly - m][lx], syy);
                 unsigned fp, fm;
-                int64_t ip = staged_nb(id, i, m, nx, 1, c.sym[0], fp), im = staged_nb(id, i, -m, nx, 1, c.sym[0], fm);
+                const int64_t ip = (int64_t)map_index(z + m, nz, c.sym[2], fp) * plane + col;
+                const int64_t im = (int64_t)map_index(z - m, nz, c.sym[2], fm) * plane + col;
                 T up = w[b * P + ip], um = w[b * P + im];
-                if (b == 0) { up = flip_sign(up, fp); um = flip_sign(um, fm); }
-                sx = fmaT(c.da[0][m - 1], up - um, sx);
-                ip = staged_nb(id, j, m, ny, sy, c.sym[1], fp);
-                im = staged_nb(id, j, -m, ny, sy, c.sym[1], fm);
-                up = w[b * P + ip];
-                um = w[b * P + im];
-                if (b == 1) { up = flip_sign(up, fp); um = flip_sign(um, fm); }
-                syy = fmaT(c.da[1][m - 1], up - um, syy);
-                ip = staged_nb(id, k, m, nz, sz, c.sym[2], fp);
-                im = staged_nb(id, k, -m, nz, sz, c.sym[2], fm);
-                up = w[b * P + ip];
-                um = w[b * P + im];
                 if (b == 2) { up = flip_sign(up, fp); um = flip_sign(um, fm); }
                 szz = fmaT(c.da[2][m - 1], up - um, szz);
             }
@@ -85,6 +235,8 @@ __global__ void __launch_bounds__(kStagedThreads)
             g[b][1] = syy;
             g[b][2] = szz;
         }
+        if (!store) continue;
+        const int64_t id = pz + col;
         const T uc[3] = {w[id], w[P + id], w[2 * P + id]};
         const T theta = g[0][0] + g[1][1] + g[2][2];
 #pragma unroll
@@ -98,74 +250,6 @@ __global__ void __launch_bounds__(kStagedThreads)
             }
             nf[jj * P + id] = v;
             nf[(3 + jj) * P + id] = theta - g[jj][jj];
-        }
-    }
-}
-
-template <typename T, int R, int MODE>
-__global__ void __launch_bounds__(kStagedThreads)
-    staged_stage_kernel(const T* __restrict__ q, const T* __restrict__ w, const T* __restrict__ nf,
-                        T* __restrict__ dq, T* __restrict__ out, const BoxConst<T> c, T dt, T A, T B,
-                        const T* __restrict__ clos, const int* __restrict__ cflag) {
-    const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
-    const int64_t P = c.P, sy = nx, sz = (int64_t)nx * ny;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // point fields of point ix with the component along axis d sign-masked
-    auto point = [&](int64_t ix, int d, unsigned f) {
-        PF<T> p;
-        p.rho = q[ix];
-        p.m0 = q[P + ix];
-        p.m1 = q[2 * P + ix];
-        p.m2 = q[3 * P + ix];
-        p.E = q[4 * P + ix];
-        p.u0 = w[ix];
-        p.u1 = w[P + ix];
-        p.u2 = w[2 * P + ix];
-        p.p = w[3 * P + ix];
-        p.Tm = w[4 * P + ix];
-        if (d == 0) { p.m0 = flip_sign(p.m0, f); p.u0 = flip_sign(p.u0, f); }
-        if (d == 1) { p.m1 = flip_sign(p.m1, f); p.u1 = flip_sign(p.u1, f); }
-        if (d == 2) { p.m2 = flip_sign(p.m2, f); p.u2 = flip_sign(p.u2, f); }
-        return p;
-    };
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < P; id += stride) {
-        const int coord[3] = {(int)(id % nx), (int)((id / nx) % ny), (int)(id / ((int64_t)nx * ny))};
-        const int64_t stv[3] = {1, sy, sz};
-        const PF<T> s = point(id, -1, 0u);
-        T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
-        static_for<3>([&](auto dd) {
-            constexpr int d = decltype(dd)::value;
-            DirSums<T> ds;
-            ds.zero();
-            // not unrolled: unrolled, the compiler requests every neighbour of the
-            // axis at once and spills the registers that needs
-#pragma unroll 1
-            for (int m = 1; m <= R; ++m) {
-                unsigned fa, fb;
-                const int64_t ia = staged_nb(id, coord[d], m, c.n[d], stv[d], c.sym[d], fa);
-                const int64_t ib = staged_nb(id, coord[d], -m, c.n[d], stv[d], c.sym[d], fb);
-                ds.template add<d>(point(ia, d, fa), flip_sign(nf[d * P + ia], fa), nf[(3 + d) * P + ia],
-                                   point(ib, d, fb), flip_sign(nf[d * P + ib], fb), nf[(3 + d) * P + ib],
-                                   c.da[d][m - 1], c.d2c[d][m - 1]);
-            }
-            ds.template finish<d>(s, c.d2c0[d], c, Rr, R0, R1, R2, RE);
-        });
-        T Rv[5] = {Rr, R0, R1, R2, RE};
-        if (clos != nullptr && cflag[0] != 0) {
-#pragma unroll
-            for (int f = 0; f < 5; ++f) Rv[f] += clos[f * P + id];
-        }
-        const T qv[5] = {s.rho, s.m0, s.m1, s.m2, s.E};
-#pragma unroll
-        for (int f = 0; f < 5; ++f) {
-            if (MODE == kModeRHS) {
-                out[f * P + id] = Rv[f];
-            } else {
-                T dn = dt * Rv[f];
-                if (MODE != kModeStage1) dn = fmaT(A, dq[f * P + id], dn);
-                if (MODE != kModeStage3) dq[f * P + id] = dn;
-                out[f * P + id] = fmaT(B, dn, qv[f]);
-            }
         }
     }
 }

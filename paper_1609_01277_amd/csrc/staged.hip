@@ -12,25 +12,29 @@ static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* w, 
     const int64_t want = (P + kStagedThreads - 1) / kStagedThreads;
     const unsigned blocks = (unsigned)(want < 1048576 ? want : 1048576);   // grid-stride beyond this
     staged_point_kernel<T><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, P, c.gm1, c.gM2);
-    staged_nested_kernel<T, R><<<blocks, kStagedThreads, 0, a.stream>>>(w, nf, c);
+    const int tx = (c.n[0] + kStagedTile - 1) / kStagedTile, ty = (c.n[1] + kStagedTile - 1) / kStagedTile;
+    const int zc = 64;
+    const unsigned grid = (unsigned)(tx * ty * ((c.n[2] + zc - 1) / zc));
+    constexpr int NT = kStagedTile * kStagedTile;
+    staged_nested_tiled_kernel<T, R><<<grid, NT, 0, a.stream>>>(w, nf, c, tx, ty, zc);
     const T dt = (T)a.dt, A = (T)a.A, B = (T)a.B;
     const T* clos = (const T*)a.clos;
     switch (a.mode) {
         case kModeRHS:
-            staged_stage_kernel<T, R, kModeRHS><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A,
-                                                                                         B, clos, a.cflag);
+            staged_tiled_kernel<T, R, kModeRHS><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+                                                                           a.cflag, tx, ty, zc);
             break;
         case kModeStage1:
-            staged_stage_kernel<T, R, kModeStage1><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
-                                                                                            A, B, clos, a.cflag);
+            staged_tiled_kernel<T, R, kModeStage1><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+                                                                              a.cflag, tx, ty, zc);
             break;
         case kModeStage2:
-            staged_stage_kernel<T, R, kModeStage2><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
-                                                                                            A, B, clos, a.cflag);
+            staged_tiled_kernel<T, R, kModeStage2><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+                                                                              a.cflag, tx, ty, zc);
             break;
         default:
-            staged_stage_kernel<T, R, kModeStage3><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt,
-                                                                                            A, B, clos, a.cflag);
+            staged_tiled_kernel<T, R, kModeStage3><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+                                                                              a.cflag, tx, ty, zc);
             break;
     }
 }
