@@ -40,13 +40,19 @@ __global__ void __launch_bounds__(kStagedThreads)
 
 // Steps 2 and 3 run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
 // (x, y) columns and a run of z-planes.  Per plane it stages what the x/y
-// stencils read, over the tile and an R-wide ring (corners excluded), into LDS,
-// so every element is loaded once instead of once per neighbour that needs it;
-// the z neighbours of the thread's own column come from memory.
+// stencils read into LDS, so every element is loaded once instead of once per
+// neighbour that needs it; the z neighbours of the thread's own column come from
+// memory.
 //
-// The residual step: point fields and the x/y nested fields staged.
+// The residual step stages one strip at a time: the tile with its x arms (TS rows
+// of TS + 2R points) for the x sums, then the tile with its y arms (TS + 2R rows of
+// TS points) in the same LDS for the y sums.  Each thread keeps its own point in
+// registers and writes it into both strips; only the arms are loaded by the
+// workgroup.  A strip holds the ten point fields and the nested pair of its axis,
+// which keeps a workgroup's LDS small enough that registers, not LDS, bound the
+// number of workgroups per CU up to order 12.
 constexpr int kStagedTile = 16;
-constexpr int kStagedFields = 14;   // rho, rho u_i, rho E, u_i, p, T, V_x, Th_x, V_y, Th_y
+constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(kStagedTile * kStagedTile)
@@ -54,8 +60,8 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
                         T* __restrict__ dq, T* __restrict__ out, const BoxConst<T> c, T dt, T A, T B,
                         const T* __restrict__ clos, const int* __restrict__ cflag, int tiles_x, int tiles_y,
                         int zchunk) {
-    constexpr int TS = kStagedTile, BW = TS + 2 * R;
-    __shared__ T sb[kStagedFields][BW][BW];
+    constexpr int TS = kStagedTile, SW = TS + 2 * R, NT = TS * TS, NA = 2 * R * TS;
+    __shared__ T sb[kStagedFields][TS * SW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P, plane = (int64_t)nx * ny;
     const int tile = blockIdx.x % (tiles_x * tiles_y);
@@ -64,9 +70,10 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
     const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;
     const bool store = x0 + cx < nx && y0 + cy < ny;
-    unsigned fdummy;
-    // own column (folded for lanes of a ragged tile; their results are not stored)
-    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fdummy) * nx + fold_index(x0 + cx, nx, c.sym[0], fdummy);
+    // own column, folded for lanes of a ragged tile: their results are not stored,
+    // but their (mirrored) points are the neighbours of the last columns inside
+    unsigned fxo, fyo;
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fyo) * nx + fold_index(x0 + cx, nx, c.sym[0], fxo);
     auto point_at = [&](int64_t ix) {
         PF<T> p;
         p.rho = q[ix];
@@ -81,66 +88,79 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
         p.Tm = w[4 * P + ix];
         return p;
     };
-    auto lds_point = [&](int ly, int lx) {
+    auto lds_point = [&](int i) {
         PF<T> p;
-        p.rho = sb[0][ly][lx];
-        p.m0 = sb[1][ly][lx];
-        p.m1 = sb[2][ly][lx];
-        p.m2 = sb[3][ly][lx];
-        p.E = sb[4][ly][lx];
-        p.u0 = sb[5][ly][lx];
-        p.u1 = sb[6][ly][lx];
-        p.u2 = sb[7][ly][lx];
-        p.p = sb[8][ly][lx];
-        p.Tm = sb[9][ly][lx];
+        p.rho = sb[0][i];
+        p.m0 = sb[1][i];
+        p.m1 = sb[2][i];
+        p.m2 = sb[3][i];
+        p.E = sb[4][i];
+        p.u0 = sb[5][i];
+        p.u1 = sb[6][i];
+        p.u2 = sb[7][i];
+        p.p = sb[8][i];
+        p.Tm = sb[9][i];
         return p;
     };
+    // a point mirrored across x (fx) and/or y (fy), and the nested pair of the strip
+    auto put = [&](int i, const PF<T>& p, unsigned fx, unsigned fy, T v, T th) {
+        sb[0][i] = p.rho;
+        sb[1][i] = flip_sign(p.m0, fx);
+        sb[2][i] = flip_sign(p.m1, fy);
+        sb[3][i] = p.m2;
+        sb[4][i] = p.E;
+        sb[5][i] = flip_sign(p.u0, fx);
+        sb[6][i] = flip_sign(p.u1, fy);
+        sb[7][i] = p.u2;
+        sb[8][i] = p.p;
+        sb[9][i] = p.Tm;
+        sb[10][i] = v;
+        sb[11][i] = th;
+    };
     for (int z = z0; z < z1; ++z) {
-        const int64_t pz = (int64_t)z * plane;
-        __syncthreads();   // the previous plane's LDS reads are done
-        for (int e = tid; e < BW * BW; e += TS * TS) {
-            const int lx = e % BW, ly = e / BW;
-            // the four R x R corners are never read
-            if ((lx < R || lx >= R + TS) && (ly < R || ly >= R + TS)) continue;
+        const int64_t pz = (int64_t)z * plane, id = pz + col;
+        const PF<T> s = point_at(id);
+        T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
+        __syncthreads();   // the previous plane's y-strip reads are done
+        put(cy * SW + R + cx, s, fxo, fyo, flip_sign(nf[id], fxo), nf[3 * P + id]);   // V_x: odd under an x mirror
+        for (int e = tid; e < NA; e += NT) {
+            const int side = e / (R * TS), r = e % (R * TS);
+            const int ly = r / R, lx = side ? R + TS + r % R : r % R;
             unsigned fx, fy;
-            const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
+            const int64_t ix = pz + (int64_t)fold_index(y0 + ly, ny, c.sym[1], fy) * nx +
                                fold_index(x0 - R + lx, nx, c.sym[0], fx);
-            const PF<T> p = point_at(ix);
-            sb[0][ly][lx] = p.rho;
-            sb[1][ly][lx] = flip_sign(p.m0, fx);
-            sb[2][ly][lx] = flip_sign(p.m1, fy);
-            sb[3][ly][lx] = p.m2;
-            sb[4][ly][lx] = p.E;
-            sb[5][ly][lx] = flip_sign(p.u0, fx);
-            sb[6][ly][lx] = flip_sign(p.u1, fy);
-            sb[7][ly][lx] = p.u2;
-            sb[8][ly][lx] = p.p;
-            sb[9][ly][lx] = p.Tm;
-            sb[10][ly][lx] = flip_sign(nf[ix], fx);            // V_x: odd under an x mirror
-            sb[11][ly][lx] = nf[3 * P + ix];                    // theta - g_xx
-            sb[12][ly][lx] = flip_sign(nf[P + ix], fy);         // V_y
-            sb[13][ly][lx] = nf[4 * P + ix];                    // theta - g_yy
+            put(ly * SW + lx, point_at(ix), fx, fy, flip_sign(nf[ix], fx), nf[3 * P + ix]);
         }
         __syncthreads();
-        const int ly = R + cy, lx = R + cx;
-        const PF<T> s = lds_point(ly, lx);
-        T Rr = 0, R0 = 0, R1 = 0, R2 = 0, RE = 0;
         {
+            const int i = cy * SW + R + cx;
             DirSums<T> ds;
             ds.zero();
 #pragma unroll 1
             for (int m = 1; m <= R; ++m)
-                ds.template add<0>(lds_point(ly, lx + m), sb[10][ly][lx + m], sb[11][ly][lx + m], lds_point(ly, lx - m),
-                                   sb[10][ly][lx - m], sb[11][ly][lx - m], c.da[0][m - 1], c.d2c[0][m - 1]);
+                ds.template add<0>(lds_point(i + m), sb[10][i + m], sb[11][i + m], lds_point(i - m), sb[10][i - m],
+                                   sb[11][i - m], c.da[0][m - 1], c.d2c[0][m - 1]);
             ds.template finish<0>(s, c.d2c0[0], c, Rr, R0, R1, R2, RE);
         }
+        __syncthreads();   // the x-strip reads are done
+        put((R + cy) * TS + cx, s, fxo, fyo, flip_sign(nf[P + id], fyo), nf[4 * P + id]);   // V_y: odd under a y mirror
+        for (int e = tid; e < NA; e += NT) {
+            const int side = e / (R * TS), r = e % (R * TS);
+            const int lx = r % TS, ly = side ? R + TS + r / TS : r / TS;
+            unsigned fx, fy;
+            const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
+                               fold_index(x0 + lx, nx, c.sym[0], fx);
+            put(ly * TS + lx, point_at(ix), fx, fy, flip_sign(nf[P + ix], fy), nf[4 * P + ix]);
+        }
+        __syncthreads();
         {
+            const int i = (R + cy) * TS + cx;
             DirSums<T> ds;
             ds.zero();
 #pragma unroll 1
             for (int m = 1; m <= R; ++m)
-                ds.template add<1>(lds_point(ly + m, lx), sb[12][ly + m][lx], sb[13][ly + m][lx], lds_point(ly - m, lx),
-                                   sb[12][ly - m][lx], sb[13][ly - m][lx], c.da[1][m - 1], c.d2c[1][m - 1]);
+                ds.template add<1>(lds_point(i + m * TS), sb[10][i + m * TS], sb[11][i + m * TS], lds_point(i - m * TS),
+                                   sb[10][i - m * TS], sb[11][i - m * TS], c.da[1][m - 1], c.d2c[1][m - 1]);
             ds.template finish<1>(s, c.d2c0[1], c, Rr, R0, R1, R2, RE);
         }
         {
@@ -162,7 +182,6 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
             ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
         }
         if (store) {
-            const int64_t id = pz + col;
             T Rv[5] = {Rr, R0, R1, R2, RE};
             if (clos != nullptr && cflag[0] != 0) {
 #pragma unroll
