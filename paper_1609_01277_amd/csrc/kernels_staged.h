@@ -54,6 +54,25 @@ __global__ void __launch_bounds__(kStagedThreads)
 constexpr int kStagedTile = 16;
 constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
+// The unit of work of a tiled launch is (tile, run of zc planes); units are
+// numbered tile by tile.  Workgroups go to the 8 XCDs round-robin by id, and XCD
+// k takes the k-th contiguous eighth of the units in order, so the workgroups
+// resident on one XCD hold neighbouring planes of the same tile at a time: the
+// z neighbours they read (2R planes on either side) are then shared in that
+// XCD's L2 instead of each workgroup streaming a window of its own through it.
+// The grid has 8 * ceil(units / 8) workgroups; the few beyond the last unit exit.
+constexpr int kStagedXcds = 8;
+
+__device__ __forceinline__ bool staged_unit(int ntiles, int nchunks, int& tile, int& chunk) {
+    const int64_t units = (int64_t)ntiles * nchunks;
+    const int64_t per = (units + kStagedXcds - 1) / kStagedXcds;
+    const int64_t u = (int64_t)(blockIdx.x % kStagedXcds) * per + blockIdx.x / kStagedXcds;
+    if (u >= units) return false;
+    tile = (int)(u / nchunks);
+    chunk = (int)(u % nchunks);
+    return true;
+}
+
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     staged_tiled_kernel(const T* __restrict__ q, const T* __restrict__ w, const T* __restrict__ nf,
@@ -64,8 +83,9 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     __shared__ T sb[kStagedFields][TS * SW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P, plane = (int64_t)nx * ny;
-    const int tile = blockIdx.x % (tiles_x * tiles_y);
-    const int z0 = (blockIdx.x / (tiles_x * tiles_y)) * zchunk;
+    int tile, chunk;
+    if (!staged_unit(tiles_x * tiles_y, (nz + zchunk - 1) / zchunk, tile, chunk)) return;
+    const int z0 = chunk * zchunk;
     const int z1 = min(z0 + zchunk, nz);
     const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
     const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;
@@ -212,8 +232,9 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     __shared__ T su[3][BW][BW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P, plane = (int64_t)nx * ny;
-    const int tile = blockIdx.x % (tiles_x * tiles_y);
-    const int z0 = (blockIdx.x / (tiles_x * tiles_y)) * zchunk;
+    int tile, chunk;
+    if (!staged_unit(tiles_x * tiles_y, (nz + zchunk - 1) / zchunk, tile, chunk)) return;
+    const int z0 = chunk * zchunk;
     const int z1 = min(z0 + zchunk, nz);
     const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
     const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;

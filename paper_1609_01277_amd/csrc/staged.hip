@@ -13,8 +13,9 @@ static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* w, 
     const unsigned blocks = (unsigned)(want < 1048576 ? want : 1048576);   // grid-stride beyond this
     staged_point_kernel<T><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, P, c.gm1, c.gM2);
     const int tx = (c.n[0] + kStagedTile - 1) / kStagedTile, ty = (c.n[1] + kStagedTile - 1) / kStagedTile;
-    const int zc = 64;
-    const unsigned grid = (unsigned)(tx * ty * ((c.n[2] + zc - 1) / zc));
+    const int zc = 1;   // one plane per workgroup: see staged_unit
+    const int64_t units = (int64_t)tx * ty * ((c.n[2] + zc - 1) / zc);
+    const unsigned grid = (unsigned)(kStagedXcds * ((units + kStagedXcds - 1) / kStagedXcds));
     constexpr int NT = kStagedTile * kStagedTile;
     staged_nested_tiled_kernel<T, R><<<grid, NT, 0, a.stream>>>(w, nf, c, tx, ty, zc);
     const T dt = (T)a.dt, A = (T)a.A, B = (T)a.B;
