@@ -54,22 +54,35 @@ __global__ void __launch_bounds__(kStagedThreads)
 constexpr int kStagedTile = 16;
 constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
-// The unit of work of a tiled launch is (tile, run of zc planes); units are
-// numbered tile by tile.  Workgroups go to the 8 XCDs round-robin by id, and XCD
-// k takes the k-th contiguous eighth of the units in order, so the workgroups
-// resident on one XCD hold neighbouring planes of the same tile at a time: the
-// z neighbours they read (2R planes on either side) are then shared in that
-// XCD's L2 instead of each workgroup streaming a window of its own through it.
-// The grid has 8 * ceil(units / 8) workgroups; the few beyond the last unit exit.
+// The unit of work of a tiled launch is (tile, run of zc planes).  Units are
+// numbered by pairs of x-adjacent tiles, plane run by plane run within a pair
+// (a last unpaired tile comes alone).  Workgroups go to the 8 XCDs round-robin
+// by id, and XCD k takes the k-th contiguous eighth of the units in order, so the
+// workgroups resident on one XCD hold neighbouring planes of the same two tiles
+// at a time: the z neighbours they read (2R planes on either side) and the x arms
+// the pair shares are then found in that XCD's L2, instead of each workgroup
+// streaming a window of its own through it.  The grid has 8 * ceil(units / 8)
+// workgroups; the few beyond the last unit exit.
 constexpr int kStagedXcds = 8;
+constexpr int kStagedPair = 2;
 
 __device__ __forceinline__ bool staged_unit(int ntiles, int nchunks, int& tile, int& chunk) {
     const int64_t units = (int64_t)ntiles * nchunks;
     const int64_t per = (units + kStagedXcds - 1) / kStagedXcds;
     const int64_t u = (int64_t)(blockIdx.x % kStagedXcds) * per + blockIdx.x / kStagedXcds;
     if (u >= units) return false;
-    tile = (int)(u / nchunks);
-    chunk = (int)(u % nchunks);
+    constexpr int G = kStagedPair;
+    const int64_t paired = (int64_t)(ntiles / G) * G * nchunks;
+    if (u < paired) {
+        const int64_t g = u / (G * nchunks), r = u % (G * nchunks);
+        chunk = (int)(r / G);
+        tile = (int)(g * G + r % G);
+    } else {   // the last ntiles % G tiles, one after the other
+        const int rest = ntiles % G;
+        const int64_t r = u - paired;
+        chunk = (int)(r / rest);
+        tile = (ntiles / G) * G + (int)(r % rest);
+    }
     return true;
 }
 

@@ -86,10 +86,13 @@ def test_order10_symmetry_matches_oracle():
     assert max(errs) <= TOL64, errs
 
 
-@pytest.mark.parametrize("dtype,bc,order", [("f64", (1, 1, 0), 4), ("f64", (0, 1, 1), 8), ("f32", (1, 0, 1), 4)])
-def test_staged_form_bitwise_equals_fused(dtype, bc, order):
+# (36, 20, 34) has 3 x 2 tiles of 16 x 16 columns, so tile pairs of the staged
+# launches span two tile rows; (36, 40, 22) has 3 x 3, which leaves one tile unpaired.
+@pytest.mark.parametrize("dtype,bc,order,n", [("f64", (1, 1, 0), 4, (36, 20, 34)), ("f64", (0, 1, 1), 8, (36, 20, 34)),
+                                              ("f32", (1, 0, 1), 4, (36, 20, 34)), ("f64", (0, 0, 0), 6, (36, 40, 22)),
+                                              ("f64", (1, 0, 1), 8, (36, 40, 22))])
+def test_staged_form_bitwise_equals_fused(dtype, bc, order, n):
     sbli, torch = _sbli()
-    n = (36, 20, 34)
     length = tuple(math.pi if b else 2 * math.pi for b in bc)
     q0 = synth.random_conservative_state(n, seed=9 + order, mom=0.4)
     tdt = torch.float64 if dtype == "f64" else torch.float32
