@@ -270,7 +270,9 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
         __syncthreads();
         const int ly = R + cy, lx = R + cx;
         T g[3][3];
-#pragma unroll
+        // one velocity component at a time: unrolled, the 6R loads of all three stay
+        // in flight together and the register count halves the workgroups per CU
+#pragma unroll 1
         for (int b = 0; b < 3; ++b) {
             T sx = 0, syy = 0, szz = 0;
 #pragma unroll
