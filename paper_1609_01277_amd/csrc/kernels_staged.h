@@ -1,5 +1,5 @@
-// Staged form of the residual and RK3 stage: three point-parallel launches with
-// the intermediate fields in HBM.  It serves every order 2..12 (the fused stage
+// Staged form of the residual and RK3 stage: three launches with the
+// intermediate fields in HBM (one thread per point in each).  It serves every order 2..12 (the fused stage
 // kernel's register window and LDS planes do not fit beyond order 8) and is a
 // launch variant of the lower orders as well, where it reproduces the fused
 // kernel bit for bit: both compute the same per-point arithmetic in the same
