@@ -1,44 +1,32 @@
-// Staged form of the residual and RK3 stage: three launches with the
-// intermediate fields in HBM (one thread per point in each).  It serves every order 2..12 (the fused stage
-// kernel's register window and LDS planes do not fit beyond order 8) and is a
-// launch variant of the lower orders as well, where it reproduces the fused
-// kernel bit for bit: both compute the same per-point arithmetic in the same
-// order (make_pf, the gradient sums, DirSums::add / finish, the 2N update).
+// Staged form of the residual and RK3 stage: two launches, one thread per
+// point, with the nested fields in HBM between them.  It serves every order
+// 2..12 (the fused stage kernel's register window and LDS planes do not fit
+// beyond order 8) and is a launch variant of the lower orders as well, where it
+// reproduces the fused kernel bit for bit: both compute the same per-point
+// arithmetic in the same order (make_pf, the gradient sums, DirSums::add /
+// finish, the 2N update).  The point fields (u_i, p, T) are recomputed by
+// make_pf from q wherever a point is read; the same function of the same inputs,
+// they are the values the fused kernel keeps in its window.
 //
-//   1. staged_point_kernel:  w = (u_0, u_1, u_2, p, T) of every point;
-//   2. staged_nested_tiled_kernel: nf = (V_0, V_1, V_2, theta - g_00,
+//   1. staged_nested_tiled_kernel: nf = (V_0, V_1, V_2, theta - g_00,
 //      theta - g_11, theta - g_22) with g_ij = D_j u_i, V_j = u_i tau_ij (paper
 //      Sec. "Expanding": the inner derivative of a nested term is taken first);
-//   3. staged_tiled_kernel:  the residual (paper eqs. of mass, momentum and
-//      energy in the skew-symmetric form) from q, w and nf at the 2R
-//      neighbours along each axis, then the 2N Runge-Kutta update.
+//   2. staged_tiled_kernel:  the residual (paper eqs. of mass, momentum and
+//      energy in the skew-symmetric form) from q and nf at the 2R neighbours
+//      along each axis, then the 2N Runge-Kutta update.
 //
 // On a symmetry axis a neighbour beyond the boundary is the mirror image of an
 // inside point; the components normal to that boundary of the momentum, the
-// velocity and V (an odd field) change sign, exactly.
+// velocity and V (an odd field) change sign, exactly.  Negating a momentum
+// component before make_pf negates the matching velocity and leaves p and T
+// unchanged, bit for bit, so the sign may be applied before or after.
 #pragma once
 
 #include "kernels_stage_fused.h"
 
 namespace sbli {
 
-constexpr int kStagedThreads = 256;
-
-template <typename T>
-__global__ void __launch_bounds__(kStagedThreads)
-    staged_point_kernel(const T* __restrict__ q, T* __restrict__ w, int64_t P, T gm1, T gM2) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; id < P; id += stride) {
-        const PF<T> f = make_pf<T>(q[id], q[P + id], q[2 * P + id], q[3 * P + id], q[4 * P + id], gm1, gM2);
-        w[id] = f.u0;
-        w[P + id] = f.u1;
-        w[2 * P + id] = f.u2;
-        w[3 * P + id] = f.p;
-        w[4 * P + id] = f.Tm;
-    }
-}
-
-// Steps 2 and 3 run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
+// Both steps run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
 // (x, y) columns and a run of z-planes.  Per plane it stages what the x/y
 // stencils read into LDS, so every element is loaded once instead of once per
 // neighbour that needs it; the z neighbours of the thread's own column come from
@@ -88,7 +76,7 @@ __device__ __forceinline__ bool staged_unit(int ntiles, int nchunks, int& tile, 
 
 template <typename T, int R, int MODE>
 __global__ void __launch_bounds__(kStagedTile * kStagedTile)
-    staged_tiled_kernel(const T* __restrict__ q, const T* __restrict__ w, const T* __restrict__ nf,
+    staged_tiled_kernel(const T* __restrict__ q, const T* __restrict__ nf,
                         T* __restrict__ dq, T* __restrict__ out, const BoxConst<T> c, T dt, T A, T B,
                         const T* __restrict__ clos, const int* __restrict__ cflag, int tiles_x, int tiles_y,
                         int zchunk) {
@@ -108,18 +96,7 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     unsigned fxo, fyo;
     const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fyo) * nx + fold_index(x0 + cx, nx, c.sym[0], fxo);
     auto point_at = [&](int64_t ix) {
-        PF<T> p;
-        p.rho = q[ix];
-        p.m0 = q[P + ix];
-        p.m1 = q[2 * P + ix];
-        p.m2 = q[3 * P + ix];
-        p.E = q[4 * P + ix];
-        p.u0 = w[ix];
-        p.u1 = w[P + ix];
-        p.u2 = w[2 * P + ix];
-        p.p = w[3 * P + ix];
-        p.Tm = w[4 * P + ix];
-        return p;
+        return make_pf<T>(q[ix], q[P + ix], q[2 * P + ix], q[3 * P + ix], q[4 * P + ix], c.gm1, c.gM2);
     };
     auto lds_point = [&](int i) {
         PF<T> p;
@@ -236,10 +213,10 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     }
 }
 
-// The nested-field step: the velocity staged.
+// The nested-field step: the velocity (u_i = rho u_i / rho, as make_pf forms it) staged.
 template <typename T, int R>
 __global__ void __launch_bounds__(kStagedTile * kStagedTile)
-    staged_nested_tiled_kernel(const T* __restrict__ w, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
+    staged_nested_tiled_kernel(const T* __restrict__ q, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
                                int tiles_y, int zchunk) {
     constexpr int TS = kStagedTile, BW = TS + 2 * R;
     __shared__ T su[3][BW][BW];
@@ -263,36 +240,36 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
             unsigned fx, fy;
             const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
                                fold_index(x0 - R + lx, nx, c.sym[0], fx);
-            su[0][ly][lx] = flip_sign(w[ix], fx);
-            su[1][ly][lx] = flip_sign(w[P + ix], fy);
-            su[2][ly][lx] = w[2 * P + ix];
+            const T rr = fast_recip(q[ix]);
+            su[0][ly][lx] = flip_sign(q[P + ix] * rr, fx);
+            su[1][ly][lx] = flip_sign(q[2 * P + ix] * rr, fy);
+            su[2][ly][lx] = q[3 * P + ix] * rr;
         }
         __syncthreads();
         const int ly = R + cy, lx = R + cx;
-        T g[3][3];
-        // one velocity component at a time: unrolled, the 6R loads of all three stay
-        // in flight together and the register count halves the workgroups per CU
+        // offset by offset, all three components: each z neighbour's density and
+        // its reciprocal are loaded and formed once (every sum still runs over m
+        // in ascending order)
+        T g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
 #pragma unroll 1
-        for (int b = 0; b < 3; ++b) {
-            T sx = 0, syy = 0, szz = 0;
+        for (int m = 1; m <= R; ++m) {
+            unsigned fp, fm;
+            const int64_t ip = (int64_t)map_index(z + m, nz, c.sym[2], fp) * plane + col;
+            const int64_t im = (int64_t)map_index(z - m, nz, c.sym[2], fm) * plane + col;
+            const T rp = fast_recip(q[ip]), rm = fast_recip(q[im]);
 #pragma unroll
-            for (int m = 1; m <= R; ++m) {
-                sx = fmaT(c.da[0][m - 1], su[b][ly][lx + m] - su[b][ly][lx - m], sx);
-                syy = fmaT(c.da[1][m - 1], su[b][ly + m][lx] - su[b][ly - m][lx], syy);
-                unsigned fp, fm;
-                const int64_t ip = (int64_t)map_index(z + m, nz, c.sym[2], fp) * plane + col;
-                const int64_t im = (int64_t)map_index(z - m, nz, c.sym[2], fm) * plane + col;
-                T up = w[b * P + ip], um = w[b * P + im];
+            for (int b = 0; b < 3; ++b) {
+                g[b][0] = fmaT(c.da[0][m - 1], su[b][ly][lx + m] - su[b][ly][lx - m], g[b][0]);
+                g[b][1] = fmaT(c.da[1][m - 1], su[b][ly + m][lx] - su[b][ly - m][lx], g[b][1]);
+                T up = q[(b + 1) * P + ip] * rp, um = q[(b + 1) * P + im] * rm;
                 if (b == 2) { up = flip_sign(up, fp); um = flip_sign(um, fm); }
-                szz = fmaT(c.da[2][m - 1], up - um, szz);
+                g[b][2] = fmaT(c.da[2][m - 1], up - um, g[b][2]);
             }
-            g[b][0] = sx;
-            g[b][1] = syy;
-            g[b][2] = szz;
         }
         if (!store) continue;
         const int64_t id = pz + col;
-        const T uc[3] = {w[id], w[P + id], w[2 * P + id]};
+        const T rc = fast_recip(q[id]);
+        const T uc[3] = {q[P + id] * rc, q[2 * P + id] * rc, q[3 * P + id] * rc};
         const T theta = g[0][0] + g[1][1] + g[2][2];
 #pragma unroll
         for (int jj = 0; jj < 3; ++jj) {

@@ -5,8 +5,8 @@
 
 namespace sbli {
 
-// Scratch words per point the staged form needs: 5 point fields + 6 nested fields.
-constexpr int kStagedScratchWords = 11;
+// Scratch words per point the staged form needs: the 6 nested fields.
+constexpr int kStagedScratchWords = 6;
 
 struct StagedArgs {
     hipStream_t stream;
@@ -20,7 +20,7 @@ struct StagedArgs {
     const int* cflag;   // device flag: the closure is added only while *cflag != 0
 };
 
-// Enqueues the three launches of one residual / RK3 stage on a.stream.
+// Enqueues the two launches of one residual / RK3 stage on a.stream.
 void staged_launch(const StagedArgs& a, const void* qin, void* dq, void* qout);
 
 }  // namespace sbli

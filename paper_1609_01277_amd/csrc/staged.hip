@@ -6,35 +6,31 @@
 namespace sbli {
 
 template <typename T, int R>
-static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* w, T* nf) {
+static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* nf) {
     const BoxConst<T>& c = *(const BoxConst<T>*)a.box;
-    const int64_t P = c.P;
-    const int64_t want = (P + kStagedThreads - 1) / kStagedThreads;
-    const unsigned blocks = (unsigned)(want < 1048576 ? want : 1048576);   // grid-stride beyond this
-    staged_point_kernel<T><<<blocks, kStagedThreads, 0, a.stream>>>(qin, w, P, c.gm1, c.gM2);
     const int tx = (c.n[0] + kStagedTile - 1) / kStagedTile, ty = (c.n[1] + kStagedTile - 1) / kStagedTile;
     const int zc = 1;   // one plane per workgroup: see staged_unit
     const int64_t units = (int64_t)tx * ty * ((c.n[2] + zc - 1) / zc);
     const unsigned grid = (unsigned)(kStagedXcds * ((units + kStagedXcds - 1) / kStagedXcds));
     constexpr int NT = kStagedTile * kStagedTile;
-    staged_nested_tiled_kernel<T, R><<<grid, NT, 0, a.stream>>>(w, nf, c, tx, ty, zc);
+    staged_nested_tiled_kernel<T, R><<<grid, NT, 0, a.stream>>>(qin, nf, c, tx, ty, zc);
     const T dt = (T)a.dt, A = (T)a.A, B = (T)a.B;
     const T* clos = (const T*)a.clos;
     switch (a.mode) {
         case kModeRHS:
-            staged_tiled_kernel<T, R, kModeRHS><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+            staged_tiled_kernel<T, R, kModeRHS><<<grid, NT, 0, a.stream>>>(qin, nf, dq, qout, c, dt, A, B, clos,
                                                                            a.cflag, tx, ty, zc);
             break;
         case kModeStage1:
-            staged_tiled_kernel<T, R, kModeStage1><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+            staged_tiled_kernel<T, R, kModeStage1><<<grid, NT, 0, a.stream>>>(qin, nf, dq, qout, c, dt, A, B, clos,
                                                                               a.cflag, tx, ty, zc);
             break;
         case kModeStage2:
-            staged_tiled_kernel<T, R, kModeStage2><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+            staged_tiled_kernel<T, R, kModeStage2><<<grid, NT, 0, a.stream>>>(qin, nf, dq, qout, c, dt, A, B, clos,
                                                                               a.cflag, tx, ty, zc);
             break;
         default:
-            staged_tiled_kernel<T, R, kModeStage3><<<grid, NT, 0, a.stream>>>(qin, w, nf, dq, qout, c, dt, A, B, clos,
+            staged_tiled_kernel<T, R, kModeStage3><<<grid, NT, 0, a.stream>>>(qin, nf, dq, qout, c, dt, A, B, clos,
                                                                               a.cflag, tx, ty, zc);
             break;
     }
@@ -42,19 +38,17 @@ static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* w, 
 
 template <typename T>
 static void staged_dispatch(const StagedArgs& a, const void* qin, void* dq, void* qout) {
-    const int64_t P = ((const BoxConst<T>*)a.box)->P;
-    T* w = (T*)a.scratch;
-    T* nf = w + 5 * P;
+    T* nf = (T*)a.scratch;
     const T* qi = (const T*)qin;
     T* d = (T*)dq;
     T* qo = (T*)qout;
     switch (a.r) {
-        case 1: staged_run<T, 1>(a, qi, d, qo, w, nf); break;
-        case 2: staged_run<T, 2>(a, qi, d, qo, w, nf); break;
-        case 3: staged_run<T, 3>(a, qi, d, qo, w, nf); break;
-        case 4: staged_run<T, 4>(a, qi, d, qo, w, nf); break;
-        case 5: staged_run<T, 5>(a, qi, d, qo, w, nf); break;
-        default: staged_run<T, 6>(a, qi, d, qo, w, nf); break;
+        case 1: staged_run<T, 1>(a, qi, d, qo, nf); break;
+        case 2: staged_run<T, 2>(a, qi, d, qo, nf); break;
+        case 3: staged_run<T, 3>(a, qi, d, qo, nf); break;
+        case 4: staged_run<T, 4>(a, qi, d, qo, nf); break;
+        case 5: staged_run<T, 5>(a, qi, d, qo, nf); break;
+        default: staged_run<T, 6>(a, qi, d, qo, nf); break;
     }
 }
 
