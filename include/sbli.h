@@ -142,10 +142,9 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  * workgroup, how far the global loads run ahead, how the register window
  * advances, the barrier schedule); together with the number of z-planes per
  * workgroup ("zchunk") they fix the launch configuration.  The last variant of
- * every (dtype, order) is the staged form: three launches, one thread per point,
- * with the point fields (5 words per point) and the nested fields (6 words per point) in
- * library-owned device memory, allocated when the form is first selected and
- * kept until sbli_destroy; orders 10 and 12 have only this variant, selected at
+ * every (dtype, order) is the staged form: two launches, one thread per point,
+ * with the nested fields (6 words per point) in library-owned device memory,
+ * allocated when the form is first selected and kept until sbli_destroy; orders 10 and 12 have only this variant, selected at
  * sbli_init.  All variants compute bitwise identical results; only speed differs.
  *
  * sbli_num_variants: number of variants for the context (>= 1), or < 0 on error.
