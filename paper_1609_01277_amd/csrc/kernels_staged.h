@@ -27,10 +27,10 @@
 namespace sbli {
 
 // Both steps run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
-// (x, y) columns and a run of z-planes.  Per plane it stages what the x/y
-// stencils read into LDS, so every element is loaded once instead of once per
-// neighbour that needs it; the z neighbours of the thread's own column come from
-// memory.
+// (x, y) columns and a run of zchunk z-planes (the launches use runs of one
+// plane; see staged_unit).  Per plane it stages what the x/y stencils read into
+// LDS, so every element is loaded once instead of once per neighbour that needs
+// it; the z neighbours of the thread's own column come from memory.
 //
 // The residual step stages one strip at a time: the tile with its x arms (TS rows
 // of TS + 2R points) for the x sums, then the tile with its y arms (TS + 2R rows of
