@@ -192,6 +192,8 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
             ds.template finish<2>(s, c.d2c0[2], c, Rr, R0, R1, R2, RE);
         }
         if (store) {
+            // dq and the new state are streamed (nothing in this launch reads them
+            // again), which leaves L2 to the z neighbours and arms of the tiles
             T Rv[5] = {Rr, R0, R1, R2, RE};
             if (clos != nullptr && cflag[0] != 0) {
 #pragma unroll
@@ -201,12 +203,12 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
 #pragma unroll
             for (int f = 0; f < 5; ++f) {
                 if (MODE == kModeRHS) {
-                    out[f * P + id] = Rv[f];
+                    __builtin_nontemporal_store(Rv[f], &out[f * P + id]);
                 } else {
                     T dn = dt * Rv[f];
-                    if (MODE != kModeStage1) dn = fmaT(A, dq[f * P + id], dn);
-                    if (MODE != kModeStage3) dq[f * P + id] = dn;
-                    out[f * P + id] = fmaT(B, dn, qv[f]);
+                    if (MODE != kModeStage1) dn = fmaT(A, __builtin_nontemporal_load(&dq[f * P + id]), dn);
+                    if (MODE != kModeStage3) __builtin_nontemporal_store(dn, &dq[f * P + id]);
+                    __builtin_nontemporal_store(fmaT(B, dn, qv[f]), &out[f * P + id]);
                 }
             }
         }
@@ -280,8 +282,8 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
                 if (ii == jj) tau = fmaT(-c.inv_Re23, theta, tau);
                 v = fmaT(uc[ii], tau, v);
             }
-            nf[jj * P + id] = v;
-            nf[(3 + jj) * P + id] = theta - g[jj][jj];
+            __builtin_nontemporal_store(v, &nf[jj * P + id]);
+            __builtin_nontemporal_store(theta - g[jj][jj], &nf[(3 + jj) * P + id]);
         }
     }
 }
