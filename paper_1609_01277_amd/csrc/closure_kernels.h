@@ -194,18 +194,31 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
     __syncthreads();
     floatx16 acc0 = {0}, acc1 = {0};
     const __bf16* wrow = Wp + (int64_t)row * Kpad;
-    const int ntap_k = 27 * CPAD;
     const int ry0 = 2 * wave;                             // tile rows ry0, ry0 + 1 of the two M tiles
-#pragma unroll 4
-    for (int k0 = 0; k0 < Kpad; k0 += 16) {
-        const int kk = k0 + half * 8;
-        const bf16x8 bv = *(const bf16x8*)(wrow + kk);
+    const int lbase = ry0 * kConvHx + row;                // this lane's point in the halo box, tap (0, 0, 0)
+    // halo-box offset of tap t (dz, dy, dx = t / 9, (t / 3) % 3, t % 3)
+    auto tap_off = [](int t) { return ((t / 9) * kConvHy + (t / 3) % 3) * kConvHx + t % 3; };
+    // The K loop runs over the packed width round_up(27 * CPAD, 16) (the value of
+    // Kpad) and is unrolled completely, so every tap offset is a constant: a step
+    // of 16 kk is one tap (channels c0 .. c0 + 15) for CPAD = 32, two taps (one
+    // per half-wave) for CPAD = 8.
+    constexpr int KP = (27 * CPAD + 15) / 16 * 16;
+#pragma unroll
+    for (int k0 = 0; k0 < KP; k0 += 16) {
+        const bf16x8 bv = *(const bf16x8*)(wrow + k0 + half * 8);
         bf16x8 a0, a1;
-        if (kk < ntap_k) {
-            const int tap = kk / CPAD, c = kk % CPAD;
-            const int dz = tap / 9, dy = (tap / 3) % 3, dx = tap % 3;   // halo-box offsets (0..2)
-            const int p0 = (dz * kConvHy + ry0 + dy) * kConvHx + row + dx;
-            const int p1 = p0 + kConvHx;                               // next row
+        const bool valid = CPAD == 32 || k0 / CPAD + half < 27;
+        if (valid) {
+            int po, c;
+            if constexpr (CPAD == 32) {
+                po = tap_off(k0 / 32);
+                c = k0 % 32 + half * 8;
+            } else {
+                po = half ? tap_off(k0 / CPAD + 1) : tap_off(k0 / CPAD);
+                c = 0;
+            }
+            const int p0 = lbase + po;
+            const int p1 = p0 + kConvHx;                  // next row
             a0 = *(const bf16x8*)(&sx[p0 * LS + c]);
             a1 = *(const bf16x8*)(&sx[p1 * LS + c]);
         } else {
