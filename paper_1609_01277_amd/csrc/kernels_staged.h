@@ -26,9 +26,10 @@
 
 namespace sbli {
 
-// Both steps run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
-// (x, y) columns and a run of zchunk z-planes (the launches use runs of one
-// plane; see staged_unit).  Per plane it stages what the x/y stencils read into
+// Both steps run in tiles: a workgroup owns a square tile of (x, y) columns
+// (nested_tile<R>() wide for the nested-field step, kStagedTile for the
+// residual step) and a run of zchunk z-planes (the launches use runs of one plane; see
+// staged_unit).  Per plane it stages what the x/y stencils read into
 // LDS, so every element is loaded once instead of once per neighbour that needs
 // it; the z neighbours of the thread's own column come from memory.
 //
@@ -40,6 +41,13 @@ namespace sbli {
 // which keeps a workgroup's LDS small enough that registers, not LDS, bound the
 // number of workgroups per CU up to order 12.
 constexpr int kStagedTile = 16;
+// The nested-field step holds three fields per LDS point and few registers, so
+// at R = 6 it takes a larger tile: 32 x 32 (1024 threads, 46 KB of LDS) stages
+// 1.75 points per output point instead of 2.5 with 16 x 16 (order 12: 2,257 ->
+// 2,305-2,345 Mpoint-steps/s at 512^3).  At R = 5 the two tile sizes measure
+// the same, and below it 16 x 16 is as fast or faster.
+template <int R>
+constexpr int nested_tile() { return R >= 6 ? 32 : 16; }
 constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
 // The unit of work of a tiled launch is (tile, run of zc planes).  Units are
@@ -216,11 +224,11 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
 }
 
 // The nested-field step: the velocity (u_i = rho u_i / rho, as make_pf forms it) staged.
-template <typename T, int R>
-__global__ void __launch_bounds__(kStagedTile * kStagedTile)
+template <typename T, int R, int TS>
+__global__ void __launch_bounds__(TS * TS)
     staged_nested_tiled_kernel(const T* __restrict__ q, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
                                int tiles_y, int zchunk) {
-    constexpr int TS = kStagedTile, BW = TS + 2 * R;
+    constexpr int BW = TS + 2 * R;
     __shared__ T su[3][BW][BW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P, plane = (int64_t)nx * ny;
