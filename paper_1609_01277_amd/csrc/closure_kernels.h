@@ -399,6 +399,9 @@ __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restri
     const int64_t stride = (int64_t)32 * Kpad32;
     float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
     int w = 0;
+    // unrolled so that many partials are in flight; each s_j still adds its
+    // partials in order of w
+#pragma unroll 8
     for (; w + 4 <= nwg; w += 4) {
         s0 += p[(w + 0) * stride];
         s1 += p[(w + 1) * stride];
@@ -447,7 +450,8 @@ __global__ void __launch_bounds__(256) bias_grad_final_kernel(const float* __res
                                                               float* __restrict__ db) {
     const int o = threadIdx.x & 31, k = threadIdx.x >> 5;
     float s = 0.0f;
-    for (int w = k; w < nwg; w += 8) s += part[w * 32 + o];
+#pragma unroll 8
+    for (int w = k; w < nwg; w += 8) s += part[w * 32 + o];   // in order of w
     __shared__ float ss[8][32];
     ss[k][o] = s;
     __syncthreads();
