@@ -203,6 +203,21 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
     // of 16 kk is one tap (channels c0 .. c0 + 15) for CPAD = 32, two taps (one
     // per half-wave) for CPAD = 8.
     constexpr int KP = (27 * CPAD + 15) / 16 * 16;
+    // the backward-data epilogue's pre-activations are requested before the K
+    // loop, so their latency is spent under the MFMAs
+    float pre[2][16];
+    if constexpr (EPI == kEpiDGelu) {
+#pragma unroll
+        for (int tt = 0; tt < 2; ++tt) {
+            const int y = y0 + 2 * wave + tt;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int m = (j / 4) * 8 + half * 4 + (j & 3);
+                const int64_t g = b * P + ((int64_t)z * n + y) * n + x0 + m;
+                pre[tt][j] = pre_in[g * 32 + row];
+            }
+        }
+    }
 #pragma unroll
     for (int k0 = 0; k0 < KP; k0 += 16) {
         const bf16x8 bv = *(const bf16x8*)(wrow + k0 + half * 8);
@@ -245,7 +260,7 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
             } else if (EPI == kEpiLinear) {
                 if (o < ocount) fout[g * ostride + o] = acc[j] + bias[o];
             } else {
-                bout[g * 32 + o] = (__bf16)(acc[j] * gelu_grad_f(pre_in[g * 32 + o]));
+                bout[g * 32 + o] = (__bf16)(acc[j] * gelu_grad_f(pre[tt][j]));
             }
         }
     }
