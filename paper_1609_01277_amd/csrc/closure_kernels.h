@@ -181,15 +181,28 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
     const int z = t % n;
     const int64_t b = t / n;
     const __bf16* inb = in + b * P * CPAD;
-    // stage the halo box: 3 x 10 x 34 points, CPAD / 8 16-byte loads each
+    // stage the halo box: 3 x 10 x 34 points, CPAD / 8 16-byte loads each.  A
+    // thread issues all of its loads before its first LDS store, so their
+    // latencies overlap instead of adding up.
     constexpr int G = CPAD / 8;
-    for (int i = threadIdx.x; i < 3 * kConvHy * kConvHx * G; i += 256) {
-        const int g = i % G;
-        const int pt = i / G;
-        const int hx = pt % kConvHx, hy = (pt / kConvHx) % kConvHy, hz = pt / (kConvHx * kConvHy);
-        const int gx = wrapn(x0 + hx - 1, n), gy = wrapn(y0 + hy - 1, n), gz = wrapn(z + hz - 1, n);
-        const bf16x8 v = *(const bf16x8*)(inb + (((int64_t)gz * n + gy) * n + gx) * CPAD + g * 8);
-        *(bf16x8*)(&sx[pt * LS + g * 8]) = v;
+    constexpr int NS = 3 * kConvHy * kConvHx * G;
+    constexpr int IT = (NS + 255) / 256;
+    bf16x8 sv[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NS) {
+            const int g = i % G;
+            const int pt = i / G;
+            const int hx = pt % kConvHx, hy = (pt / kConvHx) % kConvHy, hz = pt / (kConvHx * kConvHy);
+            const int gx = wrapn(x0 + hx - 1, n), gy = wrapn(y0 + hy - 1, n), gz = wrapn(z + hz - 1, n);
+            sv[k] = *(const bf16x8*)(inb + (((int64_t)gz * n + gy) * n + gx) * CPAD + g * 8);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < NS) *(bf16x8*)(&sx[(i / G) * LS + (i % G) * 8]) = sv[k];
     }
     __syncthreads();
     floatx16 acc0 = {0}, acc1 = {0};
