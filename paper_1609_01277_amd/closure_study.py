@@ -8,7 +8,7 @@
    (BF16 MFMA kernels of the library) on the pairs.
 3. A-posteriori: coarse 64^3 FP32 runs (dt 3.385e-3) from F q_f(0) to t = 10 with
    and without the closure; filtered kinetic energy and enstrophy against those of
-   F q_f(t) (the filtered fine solution judges the error).
+   F q_f(t) (the filtered fine solution is the reference for the error).
 
 Every arithmetic step runs in libsbli's kernels; torch only holds device memory and
 copies samples into batch buffers.  Writes one JSON file.

@@ -45,7 +45,7 @@ def test_initial_diagnostics_closed_form(oracle_mod, n, order):
         assert abs(d[1] - 3 / 8 * s_mod(order, nn) ** 2) < 1e-14
 
 
-def test_initial_enstrophy_values_survey_table(oracle_mod):
+def test_initial_enstrophy_values_at_32_and_64(oracle_mod):
     # eps_h(0) = (3/8) s^2 for the 4th-order stencil at 32^3 and 64^3
     for n, expect in ((32, 0.374963012455195), (64, 0.374997680253154)):
         p = params(n, 4)
