@@ -79,9 +79,40 @@ def conv3d_bwd_weight(x, dy):
         for dyo in (-1, 0, 1):
             for dxo in (-1, 0, 1):
                 xs = np.roll(x, shift=(-dz, -dyo, -dxo), axis=(2, 3, 4))
-                dW[:, :, dz + 1, dyo + 1, dxo + 1] = np.einsum("bozyx,bizyx->oi", dy, xs)
+                # the sum over samples and points as one library contraction
+                dW[:, :, dz + 1, dyo + 1, dxo + 1] = np.tensordot(dy, xs, axes=([0, 2, 3, 4], [0, 2, 3, 4]))
     db = dy.sum(axis=(0, 2, 3, 4))
     return dW, db
+
+
+def _taps():
+    return [(dz, dy, dx) for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def conv3d_at_points(x, W, b, pts):
+    """The convolution above evaluated only at sample/point pairs pts = [(b, z, y, x)]:
+    returns out[k, o] = b[o] + sum_{i,dz,dy,dx} W[o,i,dz+1,dy+1,dx+1] x[b_k,i,z_k+dz,y_k+dy,x_k+dx]
+    (indices wrap), gathered point by point."""
+    pts = np.asarray(pts, dtype=np.int64)
+    n = x.shape[2:]
+    out = np.tile(np.asarray(b, dtype=np.float64), (len(pts), 1))
+    for dz, dy, dx in _taps():
+        nb = x[pts[:, 0], :, (pts[:, 1] + dz) % n[0], (pts[:, 2] + dy) % n[1], (pts[:, 3] + dx) % n[2]]
+        out += nb @ W[:, :, dz + 1, dy + 1, dx + 1].T
+    return out
+
+
+def conv3d_bwd_data_at_points(dy, W, pts):
+    """conv3d_bwd_data(dy, W) at pts = [(b, z, y, x)]: out[k, i] = sum_{o,dz,dy,dx}
+    W[o,i,dz+1,dy+1,dx+1] dy[b_k, o, z_k-dz, y_k-dy, x_k-dx] (the point the tap reaches
+    this one from), gathered point by point."""
+    pts = np.asarray(pts, dtype=np.int64)
+    n = dy.shape[2:]
+    out = np.zeros((len(pts), W.shape[1]))
+    for dz, dyo, dx in _taps():
+        nb = dy[pts[:, 0], :, (pts[:, 1] - dz) % n[0], (pts[:, 2] - dyo) % n[1], (pts[:, 3] - dx) % n[2]]
+        out += nb @ W[:, :, dz + 1, dyo + 1, dx + 1]
+    return out
 
 
 def gelu(x):

@@ -114,3 +114,65 @@ def test_box_filter_conserves_mean():
     f = rng.standard_normal((5, 16, 16, 16))
     out = nn.box_filter(f, 4)
     assert np.abs(out.mean(axis=(1, 2, 3)) - f.mean(axis=(1, 2, 3))).max() < 1e-14
+
+
+def test_conv3d_at_points_equals_whole_grid():
+    """The point-by-point gather form equals the rolled whole-grid form everywhere,
+    including the wrapped faces and batch entries beyond the first."""
+    rng = np.random.default_rng(6)
+    x = rng.standard_normal((3, 4, 5, 6, 7))
+    W = rng.standard_normal((2, 4, 3, 3, 3))
+    b = rng.standard_normal(2)
+    full = nn.conv3d(x, W, b)
+    pts = [(bb, z, y, xx) for bb in range(3) for z in range(5) for y in range(6) for xx in range(7)]
+    got = nn.conv3d_at_points(x, W, b, pts)
+    ref = np.array([full[bb, :, z, y, xx] for bb, z, y, xx in pts])
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_conv3d_bwd_data_at_points_equals_whole_grid():
+    rng = np.random.default_rng(7)
+    dy = rng.standard_normal((2, 3, 4, 5, 6))
+    W = rng.standard_normal((3, 2, 3, 3, 3))
+    full = nn.conv3d_bwd_data(dy, W)
+    pts = [(bb, z, y, xx) for bb in range(2) for z in range(4) for y in range(5) for xx in range(6)]
+    got = nn.conv3d_bwd_data_at_points(dy, W, pts)
+    ref = np.array([full[bb, :, z, y, xx] for bb, z, y, xx in pts])
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_adam_constant_gradient_closed_form():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at
+    every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so each of the first three
+    steps moves p by lr g / (|g| + eps).  A bias correction with the wrong exponent
+    (for example always that of step 1) fails at t = 2."""
+    rng = np.random.default_rng(8)
+    p0 = rng.standard_normal(16)
+    g = rng.standard_normal(16)
+    lr = 1e-3
+    p, m, v = p0.copy(), np.zeros(16), np.zeros(16)
+    for t in (1, 2, 3):
+        p, m, v = nn.adam_step(p, g, m, v, t, lr)
+        assert np.abs(p - (p0 - t * lr * g / (np.abs(g) + 1e-8))).max() < 1e-14, t
+
+
+def test_adam_second_step_closed_forms():
+    """Second step after g1, by hand from the definitions:
+    g2 = 0:    m2^ = b1/(1+b1) g1, v2^ = b2/(1+b2) g1^2;
+    g2 = -g1:  m2^ = -(1-b1)/(1+b1) g1, v2^ = g1^2."""
+    rng = np.random.default_rng(9)
+    g1 = rng.standard_normal(12)
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    p0 = rng.standard_normal(12)
+    p1, m1, v1 = nn.adam_step(p0.copy(), g1, np.zeros(12), np.zeros(12), 1, lr)
+    p2, _, _ = nn.adam_step(p1.copy(), np.zeros(12), m1.copy(), v1.copy(), 2, lr)
+    ref = p1 - lr * (b1 / (1 + b1)) * g1 / (np.sqrt(b2 / (1 + b2)) * np.abs(g1) + eps)
+    assert np.abs(p2 - ref).max() < 1e-14
+    p2, m2, v2 = nn.adam_step(p1.copy(), -g1, m1.copy(), v1.copy(), 2, lr)
+    ref = p1 + lr * ((1 - b1) / (1 + b1)) * g1 / (np.abs(g1) + eps)
+    assert np.abs(p2 - ref).max() < 1e-14
+    # third step with g3 = g1 after (g1, -g1): m3 = (1-b1)(b1^2 - b1 + 1) g1
+    p3, _, _ = nn.adam_step(p2.copy(), g1, m2.copy(), v2.copy(), 3, lr)
+    mh = (1 - b1) * (b1 * b1 - b1 + 1) / (1 - b1 ** 3) * g1
+    vh = (1 - b2) * (b2 * b2 + b2 + 1) / (1 - b2 ** 3) * g1 * g1
+    assert np.abs(p3 - (p2 - lr * mh / (np.sqrt(vh) + eps))).max() < 1e-14
