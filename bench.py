@@ -233,8 +233,9 @@ def main():
         torch.cuda.synchronize()
         log("copied %d MiB x 5" % args.calibrate_copy)
         return
-    from paper_1609_01277_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
+    from paper_1609_01277_amd import build as libbuild
+    if not libbuild.is_current():
+        # missing, or built from other sources than those in the tree
         import __graft_entry__
         __graft_entry__.build()
     import paper_1609_01277_amd as sbli

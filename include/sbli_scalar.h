@@ -11,7 +11,10 @@
  * periodic grid of n[0] x n[1] x n[2] points (x fastest; an axis with one point is
  * inactive), spacing length[d] / n[d], constant velocity c and diffusivity k >= 0,
  * and an optional source S (device array of the grid's size, or NULL).
- * Every active axis needs n >= p + 1.  phi, phi_tmp, dphi, source and rhs are
+ * Every active axis needs n >= 2; indices wrap modulo n as often as the stencil
+ * needs, so a stencil wider than the grid (the manufactured-solution study's
+ * coarsest grids, 4 points at order 12) is the periodic operator on those points.
+ * phi, phi_tmp, dphi, source and rhs are
  * FP64 device arrays of n[0] n[1] n[2] values; work is enqueued on hip_stream.
  * Errors: SBLI_ERR_ARG / SBLI_ERR_HIP with a message from sbli_scalar_last_error
  * (per calling thread).

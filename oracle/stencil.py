@@ -16,6 +16,7 @@ elimination over Fractions.
       exact for f = x^(2l),   l = 1..r    ->  sum_m c_m m^(2l)      = [l == 1]
       and for f = 1                        ->  c_0 = -2 sum_m c_m
 """
+import functools
 from fractions import Fraction
 
 
@@ -35,20 +36,33 @@ def _solve(mat, rhs):
 
 def first_derivative_weights(order):
     """a_1..a_r of the order-`order` central first derivative (order even)."""
+    return list(_first_derivative_weights(order))
+
+
+def second_derivative_weights(order):
+    """(c_0, [c_1..c_r]) of the order-`order` central second derivative."""
+    c0, c = _second_derivative_weights(order)
+    return c0, list(c)
+
+
+# The exact solves are repeated for every call of the oracle; their results are
+# remembered per order (the weights are pure functions of it).
+@functools.lru_cache(maxsize=None)
+def _first_derivative_weights(order):
     if order < 2 or order % 2:
         raise ValueError("order must be a positive even integer")
     r = order // 2
     mat = [[2 * Fraction(m) ** (2 * l + 1) for m in range(1, r + 1)] for l in range(r)]
     rhs = [1 if l == 0 else 0 for l in range(r)]
-    return _solve(mat, rhs)
+    return tuple(_solve(mat, rhs))
 
 
-def second_derivative_weights(order):
-    """(c_0, [c_1..c_r]) of the order-`order` central second derivative."""
+@functools.lru_cache(maxsize=None)
+def _second_derivative_weights(order):
     if order < 2 or order % 2:
         raise ValueError("order must be a positive even integer")
     r = order // 2
     mat = [[Fraction(m) ** (2 * l) for m in range(1, r + 1)] for l in range(1, r + 1)]
     rhs = [1 if l == 1 else 0 for l in range(1, r + 1)]
     c = _solve(mat, rhs)
-    return -2 * sum(c), c
+    return -2 * sum(c), tuple(c)

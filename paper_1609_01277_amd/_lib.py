@@ -49,6 +49,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError("libsbli.so is not built (%s); run __graft_entry__.build() or "
                           "python paper_1609_01277_amd/build.py" % LIB_PATH)
+    from . import build as _build
+    if not _build.is_current():
+        raise ImportError("libsbli.so (%s) was not built from the current sources under csrc/ and "
+                          "include/; rebuild it with __graft_entry__.build() or "
+                          "python paper_1609_01277_amd/build.py" % LIB_PATH)
     lib = ctypes.CDLL(LIB_PATH)
     vp = ctypes.c_void_p
     lib.sbli_init.argtypes = [ctypes.POINTER(sbli_params), vp, ctypes.POINTER(vp)]

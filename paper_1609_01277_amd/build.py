@@ -30,6 +30,34 @@ SOURCE_FLAGS = {
 }
 
 
+STAMP = LIB + ".sources"   # digest of the sources and flags the library was built from
+
+
+def sources_digest():
+    """sha256 over every file under csrc/ and include/, the compiler flags and the
+    source list: what a build of libsbli.so depends on."""
+    import hashlib
+    h = hashlib.sha256()
+    h.update(repr((HIPCC_FLAGS, SOURCE_FLAGS, SOURCES)).encode())
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            path = os.path.join(d, name)
+            if os.path.isfile(path) and not name.startswith("."):
+                h.update(name.encode())
+                with open(path, "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()
+
+
+def is_current():
+    """True when libsbli.so exists and was built from the sources as they are now."""
+    try:
+        with open(STAMP) as f:
+            return os.path.exists(LIB) and f.read().strip() == sources_digest()
+    except OSError:
+        return False
+
+
 def hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", "hipcc"):
         if cand and (os.path.sep not in cand or os.path.exists(cand)):
@@ -70,7 +98,11 @@ def build(verbose=False):
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + _clean(res.stdout))
+    digest = sources_digest()
     os.replace(tmp, LIB)
+    with open(STAMP + ".tmp", "w") as f:
+        f.write(digest + "\n")
+    os.replace(STAMP + ".tmp", STAMP)
     return LIB
 
 

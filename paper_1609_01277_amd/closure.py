@@ -39,6 +39,26 @@ def _L():
         lib.sbli_net_guard.argtypes = [vp, vp, vp, vp]
         lib.sbli_box_filter.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
                                         ctypes.c_int, vp]
+        lib.sbli_net_stream.argtypes = [vp]
+        lib.sbli_net_stream.restype = vp
+        ll, i = ctypes.c_longlong, ctypes.c_int
+        lib.sbli_conv3d_cpad.argtypes = [i]
+        lib.sbli_conv3d_packed_width.argtypes = [i]
+        lib.sbli_conv3d_pack.argtypes = [vp, i, i, vp, vp, vp]
+        lib.sbli_conv3d_fwd.argtypes = [vp, i, vp, vp, i, i, i, i, vp, vp, vp]
+        lib.sbli_conv3d_bwd_data.argtypes = [vp, i, vp, i, i, vp, vp, vp]
+        lib.sbli_gelu_bwd.argtypes = [vp, vp, ll, vp, vp]
+        lib.sbli_conv3d_bwd_weight_work_bytes.argtypes = [i]
+        lib.sbli_conv3d_bwd_weight_work_bytes.restype = ll
+        lib.sbli_conv3d_bwd_weight.argtypes = [vp, i, vp, i, i, i, vp, vp, vp, ll, vp]
+        lib.sbli_mse_grad_work_bytes.argtypes = [i, i]
+        lib.sbli_mse_grad_work_bytes.restype = ll
+        lib.sbli_mse_grad.argtypes = [vp, i, vp, vp, i, i, vp, vp, vp, ll, vp]
+        lib.sbli_adam_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, i, vp]
+        for name in ("sbli_conv3d_cpad", "sbli_conv3d_packed_width", "sbli_conv3d_pack", "sbli_conv3d_fwd",
+                     "sbli_conv3d_bwd_data", "sbli_gelu_bwd", "sbli_conv3d_bwd_weight", "sbli_mse_grad",
+                     "sbli_adam_step"):
+            getattr(lib, name).restype = ctypes.c_int
         lib.sbli_closure_attach.argtypes = [vp, vp]
         lib.sbli_closure_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_uint)]
         for name in ("sbli_net_create", "sbli_net_destroy", "sbli_net_num_params", "sbli_net_n",
@@ -71,6 +91,71 @@ def sbli_box_filter(fine, nf, nfields, ratio, coarse, subtract=False, stream=Non
     _check(_L().sbli_box_filter(fine.data_ptr(), dt, int(nf), int(nfields), int(ratio), coarse.data_ptr(),
                                 1 if subtract else 0, stream))
     return coarse
+
+
+# ---- the network's kernels, one entry point each (device tensors, current stream) ----
+ACT_NONE = 0
+ACT_GELU = 1
+
+
+def _stream(stream):
+    import torch
+    return torch.cuda.current_stream().cuda_stream if stream is None else stream
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def sbli_conv3d_cpad(channels):
+    return _L().sbli_conv3d_cpad(int(channels))
+
+
+def sbli_conv3d_packed_width(channels):
+    return _L().sbli_conv3d_packed_width(int(channels))
+
+
+def sbli_conv3d_pack(W, cin, cout, Wf, Wb, stream=None):
+    _check(_L().sbli_conv3d_pack(W.data_ptr(), int(cin), int(cout), _ptr(Wf), _ptr(Wb), _stream(stream)))
+
+
+def sbli_conv3d_fwd(x, cin, Wf, b, cout, n, batch, act, pre, h=None, stream=None):
+    _check(_L().sbli_conv3d_fwd(x.data_ptr(), int(cin), Wf.data_ptr(), b.data_ptr(), int(cout), int(n), int(batch),
+                                int(act), pre.data_ptr(), _ptr(h), _stream(stream)))
+
+
+def sbli_conv3d_bwd_data(dy, cout, Wb, n, batch, pre, dx, stream=None):
+    _check(_L().sbli_conv3d_bwd_data(dy.data_ptr(), int(cout), Wb.data_ptr(), int(n), int(batch), _ptr(pre),
+                                     dx.data_ptr(), _stream(stream)))
+
+
+def sbli_gelu_bwd(g, pre, count, dx, stream=None):
+    _check(_L().sbli_gelu_bwd(g.data_ptr(), pre.data_ptr(), int(count), dx.data_ptr(), _stream(stream)))
+
+
+def sbli_conv3d_bwd_weight_work_bytes(cin):
+    return _L().sbli_conv3d_bwd_weight_work_bytes(int(cin))
+
+
+def sbli_conv3d_bwd_weight(x, cin, dy, cout, n, batch, dW, db, work, stream=None):
+    _check(_L().sbli_conv3d_bwd_weight(x.data_ptr(), int(cin), dy.data_ptr(), int(cout), int(n), int(batch),
+                                       dW.data_ptr(), _ptr(db), work.data_ptr(),
+                                       work.numel() * work.element_size(), _stream(stream)))
+
+
+def sbli_mse_grad_work_bytes(n, batch):
+    return _L().sbli_mse_grad_work_bytes(int(n), int(batch))
+
+
+def sbli_mse_grad(y, ystride, t, mean_std, n, batch, dy, loss, work, stream=None):
+    _check(_L().sbli_mse_grad(y.data_ptr(), int(ystride), t.data_ptr(), mean_std.data_ptr(), int(n), int(batch),
+                              dy.data_ptr(), loss.data_ptr(), work.data_ptr(), work.numel() * work.element_size(),
+                              _stream(stream)))
+
+
+def sbli_adam_step(p, g, m, v, count, lr, t, stream=None):
+    _check(_L().sbli_adam_step(p.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), int(count), float(lr),
+                               int(t), _stream(stream)))
 
 
 class ClosureNet:

@@ -20,6 +20,8 @@ constexpr int kCpad[4] = {8, 32, 32, 8};    // padded channel strides of the act
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
+constexpr int kWgradWg = 512;   // workgroups of the weight-gradient kernel (fixed, so the sum order is fixed)
+
 struct Layer {
     int cin, cout, cpad, opad;   // real and padded input / output channels
     int Kf, Kb, Kpad32;          // packed forward / backward-data widths, weight-gradient width
@@ -44,7 +46,7 @@ struct sbli_net {
     float *pre1 = nullptr, *pre2 = nullptr, *y = nullptr;
     float* wpart = nullptr;          // weight-gradient partials
     float* bpart = nullptr;          // bias-gradient partials [kBiasWg][32]
-    int wgrad_wg = 512;
+    int wgrad_wg = kWgradWg;
     double* loss_part = nullptr;
     double* loss = nullptr;
     std::string err;
@@ -243,17 +245,39 @@ extern "C" int sbli_net_get_stats(sbli_net* net, float* host_stats) {
 }
 
 // One convolution (implicit GEMM on MFMA, input staged in LDS): `in` has cpad
-// channels per point (8 or 32), epilogue EPI (see closure_kernels.h).
+// channels per point (8 or 32), epilogue EPI (see closure_kernels.h).  The
+// network and the per-kernel exports launch it through here.
+template <int EPI>
+static void conv_launch(hipStream_t stream, int n, const __bf16* in, int cpad, const __bf16* W, int Kpad,
+                        const float* bias, int batch, float* fout, __bf16* bout, const float* pre_in, int ocount,
+                        int ostride) {
+    const unsigned g = (unsigned)((int64_t)batch * n * (n / kConvTy) * (n / kConvTx));
+    if (cpad == 32)
+        conv_mfma_lds_kernel<EPI, 32><<<g, 256, 0, stream>>>(in, W, Kpad, bias, n, fout, bout, pre_in, ocount,
+                                                              ostride);
+    else
+        conv_mfma_lds_kernel<EPI, 8><<<g, 256, 0, stream>>>(in, W, Kpad, bias, n, fout, bout, pre_in, ocount,
+                                                             ostride);
+}
+
 template <int EPI>
 static void conv(sbli_net* net, const __bf16* in, int cpad, const __bf16* W, int Kpad, const float* bias, int batch,
                  float* fout, __bf16* bout, const float* pre_in, int ocount, int ostride) {
-    const unsigned g = (unsigned)((int64_t)batch * net->n * (net->n / kConvTy) * (net->n / kConvTx));
-    if (cpad == 32)
-        conv_mfma_lds_kernel<EPI, 32><<<g, 256, 0, net->stream>>>(in, W, Kpad, bias, net->n, fout, bout, pre_in,
-                                                                  ocount, ostride);
-    else
-        conv_mfma_lds_kernel<EPI, 8><<<g, 256, 0, net->stream>>>(in, W, Kpad, bias, net->n, fout, bout, pre_in,
-                                                                 ocount, ostride);
+    conv_launch<EPI>(net->stream, net->n, in, cpad, W, Kpad, bias, batch, fout, bout, pre_in, ocount, ostride);
+}
+
+// Weight and bias gradients of one layer: per-workgroup partials, then fixed-order
+// reductions into dW (master layout) and db.
+static void wgrad_launch(hipStream_t stream, int n, int batch, const __bf16* in, int cpad, int cin, const __bf16* dout,
+                         int opad, int cout, int nwg, float* wpart, float* bpart, float* dW, float* db) {
+    const int Kpad32 = round_up(27 * cpad, 32);
+    const int64_t blocks = (int64_t)batch * n * n * (n / 32);
+    conv_wgrad_kernel<<<nwg, 256, 0, stream>>>(in, cpad, dout, opad, n, blocks, Kpad32, wpart);
+    wgrad_reduce_kernel<<<nblk(cout * Kpad32), 256, 0, stream>>>(wpart, nwg, Kpad32, cpad, cin, cout, dW);
+    if (db) {
+        bias_grad_kernel<<<kBiasWg, 256, 0, stream>>>(dout, opad, (int64_t)batch * n * n * n, bpart);
+        bias_grad_final_kernel<<<1, 256, 0, stream>>>(bpart, kBiasWg, cout, db);
+    }
 }
 
 // Forward pass of `batch` samples: x -> h1 -> h2 -> y (all in the net's buffers).
@@ -285,14 +309,8 @@ extern "C" int sbli_net_forward(sbli_net* net, const float* q, int batch, float*
 
 static int wgrad(sbli_net* net, int l, const __bf16* in, const __bf16* dout, int batch) {
     const Layer& L = net->L[l];
-    const int64_t blocks = (int64_t)batch * net->n * net->n * (net->n / 32);
-    conv_wgrad_kernel<<<net->wgrad_wg, 256, 0, net->stream>>>(in, L.cpad, dout, L.opad, net->n, blocks, L.Kpad32,
-                                                              net->wpart);
-    wgrad_reduce_kernel<<<nblk(L.cout * L.Kpad32), 256, 0, net->stream>>>(net->wpart, net->wgrad_wg, L.Kpad32,
-                                                                         L.cpad, L.cin, L.cout,
-                                                                         net->grads + L.w_off);
-    bias_grad_kernel<<<kBiasWg, 256, 0, net->stream>>>(dout, L.opad, (int64_t)batch * net->P, net->bpart);
-    bias_grad_final_kernel<<<1, 256, 0, net->stream>>>(net->bpart, kBiasWg, L.cout, net->grads + L.b_off);
+    wgrad_launch(net->stream, net->n, batch, in, L.cpad, L.cin, dout, L.opad, L.cout, net->wgrad_wg, net->wpart,
+                 net->bpart, net->grads + L.w_off, net->grads + L.b_off);
     NHIP_TRY(net, hipGetLastError());
     return SBLI_OK;
 }
@@ -352,6 +370,8 @@ extern "C" int sbli_net_guard(sbli_net* net, const float* c, int* flag, unsigned
 
 extern "C" int sbli_net_n(const sbli_net* net) { return net ? net->n : SBLI_ERR_ARG; }
 
+extern "C" void* sbli_net_stream(const sbli_net* net) { return net ? (void*)net->stream : nullptr; }
+
 extern "C" int sbli_box_filter(const void* fine, int dtype, int nf, int nfields, int ratio, float* coarse,
                                int subtract, void* hip_stream) {
     if (!fine || !coarse) return nfail(nullptr, SBLI_ERR_ARG, "sbli_box_filter: NULL pointer");
@@ -370,4 +390,151 @@ extern "C" int sbli_box_filter(const void* fine, int dtype, int nf, int nfields,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "sbli_box_filter: %s", hipGetErrorString(e));
     return SBLI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The network's kernels as separate entry points (explicit pointers, shapes and
+// stream).  Each validates its shapes on the host and launches exactly the
+// kernels the network runs.
+
+static int conv_cpad(int c) { return c >= 1 && c <= 8 ? 8 : (c >= 9 && c <= 32 ? 32 : -1); }
+
+static int check_grid(const char* fn, int n, int batch) {
+    if (n < 32 || n % 32 != 0 || n > 1024)
+        return nfail(nullptr, SBLI_ERR_ARG, "%s: n must be a multiple of 32 in [32, 1024] (got %d)", fn, n);
+    if (batch < 1 || (int64_t)batch * n * n * n > (int64_t)1 << 31)
+        return nfail(nullptr, SBLI_ERR_ARG, "%s: batch must be >= 1 with batch * n^3 <= 2^31", fn);
+    return SBLI_OK;
+}
+
+static int launch_status(const char* fn) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "%s: %s", fn, hipGetErrorString(e));
+    return SBLI_OK;
+}
+
+extern "C" int sbli_conv3d_cpad(int channels) {
+    const int c = conv_cpad(channels);
+    return c > 0 ? c : nfail(nullptr, SBLI_ERR_ARG, "sbli_conv3d_cpad: channels must be in [1, 32]");
+}
+
+extern "C" int sbli_conv3d_packed_width(int channels) {
+    const int c = conv_cpad(channels);
+    if (c < 0) return nfail(nullptr, SBLI_ERR_ARG, "sbli_conv3d_packed_width: channels must be in [1, 32]");
+    return round_up(27 * c, 16);
+}
+
+extern "C" int sbli_conv3d_pack(const float* W, int cin, int cout, void* Wf, void* Wb, void* hip_stream) {
+    if (!W || (!Wf && !Wb)) return nfail(nullptr, SBLI_ERR_ARG, "sbli_conv3d_pack: NULL argument");
+    const int cpad = conv_cpad(cin), opad = conv_cpad(cout);
+    if (cpad < 0 || opad < 0) return nfail(nullptr, SBLI_ERR_ARG, "sbli_conv3d_pack: cin, cout must be in [1, 32]");
+    const int Kf = round_up(27 * cpad, 16), Kb = round_up(27 * opad, 16);
+    pack_weights_kernel<<<nblk(32 * (Kf > Kb ? Kf : Kb)), 256, 0, (hipStream_t)hip_stream>>>(
+        W, cin, cout, cpad, opad, Kf, Kb, (__bf16*)Wf, (__bf16*)Wb);
+    return launch_status("sbli_conv3d_pack");
+}
+
+extern "C" int sbli_conv3d_fwd(const void* x, int cin, const void* Wf, const float* b, int cout, int n, int batch,
+                               int act, float* pre, void* h, void* hip_stream) {
+    const char* fn = "sbli_conv3d_fwd";
+    if (!x || !Wf || !b || !pre) return nfail(nullptr, SBLI_ERR_ARG, "%s: NULL argument", fn);
+    int rc = check_grid(fn, n, batch);
+    if (rc != SBLI_OK) return rc;
+    const int cpad = conv_cpad(cin), opad = conv_cpad(cout);
+    if (cpad < 0 || opad < 0) return nfail(nullptr, SBLI_ERR_ARG, "%s: cin, cout must be in [1, 32]", fn);
+    const int Kf = round_up(27 * cpad, 16);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (act == SBLI_ACT_GELU) {
+        if (cout != 32 || !h) return nfail(nullptr, SBLI_ERR_ARG, "%s: GELU layers need cout = 32 and h", fn);
+        conv_launch<kEpiGelu>(s, n, (const __bf16*)x, cpad, (const __bf16*)Wf, Kf, b, batch, pre, (__bf16*)h,
+                              nullptr, 32, 32);
+    } else if (act == SBLI_ACT_NONE) {
+        conv_launch<kEpiLinear>(s, n, (const __bf16*)x, cpad, (const __bf16*)Wf, Kf, b, batch, pre, nullptr,
+                                nullptr, cout, opad);
+    } else {
+        return nfail(nullptr, SBLI_ERR_ARG, "%s: act must be SBLI_ACT_NONE or SBLI_ACT_GELU", fn);
+    }
+    return launch_status(fn);
+}
+
+extern "C" int sbli_conv3d_bwd_data(const void* dy, int cout, const void* Wb, int n, int batch, const float* pre,
+                                    void* dx, void* hip_stream) {
+    const char* fn = "sbli_conv3d_bwd_data";
+    if (!dy || !Wb || !dx) return nfail(nullptr, SBLI_ERR_ARG, "%s: NULL argument", fn);
+    int rc = check_grid(fn, n, batch);
+    if (rc != SBLI_OK) return rc;
+    const int opad = conv_cpad(cout);
+    if (opad < 0) return nfail(nullptr, SBLI_ERR_ARG, "%s: cout must be in [1, 32]", fn);
+    const int Kb = round_up(27 * opad, 16);
+    hipStream_t s = (hipStream_t)hip_stream;
+    if (pre)
+        conv_launch<kEpiDGelu>(s, n, (const __bf16*)dy, opad, (const __bf16*)Wb, Kb, nullptr, batch, nullptr,
+                               (__bf16*)dx, pre, 32, 32);
+    else
+        conv_launch<kEpiData>(s, n, (const __bf16*)dy, opad, (const __bf16*)Wb, Kb, nullptr, batch, (float*)dx,
+                              nullptr, nullptr, 32, 32);
+    return launch_status(fn);
+}
+
+extern "C" int sbli_gelu_bwd(const float* g, const float* pre, long long count, void* dx, void* hip_stream) {
+    if (!g || !pre || !dx) return nfail(nullptr, SBLI_ERR_ARG, "sbli_gelu_bwd: NULL argument");
+    if (count < 0) return nfail(nullptr, SBLI_ERR_ARG, "sbli_gelu_bwd: count < 0");
+    if (count == 0) return SBLI_OK;
+    gelu_bwd_kernel<<<nblk(count), 256, 0, (hipStream_t)hip_stream>>>(g, pre, count, (__bf16*)dx);
+    return launch_status("sbli_gelu_bwd");
+}
+
+extern "C" long long sbli_conv3d_bwd_weight_work_bytes(int cin) {
+    const int cpad = conv_cpad(cin);
+    if (cpad < 0) return nfail(nullptr, SBLI_ERR_ARG, "sbli_conv3d_bwd_weight_work_bytes: cin must be in [1, 32]");
+    return (long long)sizeof(float) * ((long long)kWgradWg * 32 * round_up(27 * cpad, 32) + (long long)kBiasWg * 32);
+}
+
+extern "C" int sbli_conv3d_bwd_weight(const void* x, int cin, const void* dy, int cout, int n, int batch, float* dW,
+                                      float* db, void* work, long long work_bytes, void* hip_stream) {
+    const char* fn = "sbli_conv3d_bwd_weight";
+    if (!x || !dy || !dW || !work) return nfail(nullptr, SBLI_ERR_ARG, "%s: NULL argument", fn);
+    int rc = check_grid(fn, n, batch);
+    if (rc != SBLI_OK) return rc;
+    const int cpad = conv_cpad(cin), opad = conv_cpad(cout);
+    if (cpad < 0 || opad < 0) return nfail(nullptr, SBLI_ERR_ARG, "%s: cin, cout must be in [1, 32]", fn);
+    const long long need = sbli_conv3d_bwd_weight_work_bytes(cin);
+    if (work_bytes < need) return nfail(nullptr, SBLI_ERR_ARG, "%s: work holds %lld bytes, %lld needed", fn, work_bytes, need);
+    float* wpart = (float*)work;
+    float* bpart = wpart + (size_t)kWgradWg * 32 * round_up(27 * cpad, 32);
+    wgrad_launch((hipStream_t)hip_stream, n, batch, (const __bf16*)x, cpad, cin, (const __bf16*)dy, opad, cout,
+                 kWgradWg, wpart, bpart, dW, db);
+    return launch_status(fn);
+}
+
+extern "C" long long sbli_mse_grad_work_bytes(int n, int batch) {
+    if (check_grid("sbli_mse_grad_work_bytes", n, batch) != SBLI_OK) return SBLI_ERR_ARG;
+    return (long long)sizeof(double) * nblk((int64_t)batch * n * n * n);
+}
+
+extern "C" int sbli_mse_grad(const float* y, int ystride, const float* t, const float* mean_std, int n, int batch,
+                             void* dy, double* loss, void* work, long long work_bytes, void* hip_stream) {
+    const char* fn = "sbli_mse_grad";
+    if (!y || !t || !mean_std || !dy || !loss || !work) return nfail(nullptr, SBLI_ERR_ARG, "%s: NULL argument", fn);
+    int rc = check_grid(fn, n, batch);
+    if (rc != SBLI_OK) return rc;
+    if (ystride != 8) return nfail(nullptr, SBLI_ERR_ARG, "%s: ystride must be 8 (the padded output layout)", fn);
+    const int64_t NP = (int64_t)batch * n * n * n;
+    if (work_bytes < (long long)sizeof(double) * nblk(NP))
+        return nfail(nullptr, SBLI_ERR_ARG, "%s: work is too small", fn);
+    hipStream_t s = (hipStream_t)hip_stream;
+    const unsigned g = nblk(NP);
+    mse_grad_kernel<<<g, 256, 0, s>>>(y, t, (int64_t)n * n * n, batch, mean_std, (__bf16*)dy, (double*)work);
+    sum_doubles_kernel<<<1, 256, 0, s>>>((const double*)work, (int)g, 1.0 / (5.0 * (double)NP), loss);
+    return launch_status(fn);
+}
+
+extern "C" int sbli_adam_step(float* p, const float* g, float* m, float* v, int count, float lr, int t,
+                              void* hip_stream) {
+    if (!p || !g || !m || !v) return nfail(nullptr, SBLI_ERR_ARG, "sbli_adam_step: NULL argument");
+    if (count < 0 || t < 1 || !(lr > 0) || !std::isfinite(lr))
+        return nfail(nullptr, SBLI_ERR_ARG, "sbli_adam_step: count >= 0, t >= 1 and lr > 0 required");
+    if (count == 0) return SBLI_OK;
+    adam_kernel<<<nblk(count), 256, 0, (hipStream_t)hip_stream>>>(p, g, m, v, count, lr, 0.9f, 0.999f, 1e-8f, t);
+    return launch_status("sbli_adam_step");
 }

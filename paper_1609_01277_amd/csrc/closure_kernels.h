@@ -147,7 +147,8 @@ __global__ void __launch_bounds__(256) destandardize_kernel(const float* __restr
 //   kEpiGelu   : v = acc + bias; pre[..][o] = v (FP32, 32 ch); act[..][o] = bf16(gelu v)
 //   kEpiLinear : v = acc + bias; y[..][o] = v (FP32, ostride ch) for o < ocount
 //   kEpiDGelu  : v = acc * gelu'(pre[..][o]); act[..][o] = bf16(v) (32 ch)
-enum { kEpiGelu = 0, kEpiLinear = 1, kEpiDGelu = 2 };
+//   kEpiData   : out[..][o] = acc (FP32, 32 ch)
+enum { kEpiGelu = 0, kEpiLinear = 1, kEpiDGelu = 2, kEpiData = 3 };
 
 // The input is staged in LDS (grids with n % 32 == 0).  A workgroup owns 32
 // x-points x 8 y-rows of one z-plane of one sample (256 points; wave w takes
@@ -272,11 +273,21 @@ __global__ void __launch_bounds__(256) conv_mfma_lds_kernel(const __bf16* __rest
                 bout[g * 32 + o] = (__bf16)gelu_f(v);
             } else if (EPI == kEpiLinear) {
                 if (o < ocount) fout[g * ostride + o] = acc[j] + bias[o];
+            } else if (EPI == kEpiData) {
+                fout[g * 32 + o] = acc[j];
             } else {
                 bout[g * 32 + o] = (__bf16)(acc[j] * gelu_grad_f(pre[tt][j]));
             }
         }
     }
+}
+
+// Element-wise GELU backward: dx = bf16(g * gelu'(pre)), the arithmetic of the
+// kEpiDGelu epilogue.
+__global__ void __launch_bounds__(256) gelu_bwd_kernel(const float* __restrict__ g, const float* __restrict__ pre,
+                                                       int64_t count, __bf16* __restrict__ dx) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) dx[i] = (__bf16)(g[i] * gelu_grad_f(pre[i]));
 }
 
 // ---------------------------------------------------------------------------
@@ -562,14 +573,14 @@ __global__ void __launch_bounds__(256) pack_weights_kernel(const float* __restri
                                                            int opad, int Kf, int Kb, __bf16* __restrict__ Wf,
                                                            __bf16* __restrict__ Wb) {
     const int id = blockIdx.x * blockDim.x + threadIdx.x;
-    if (id < 32 * Kf) {
+    if (Wf != nullptr && id < 32 * Kf) {
         const int o = id / Kf, kk = id % Kf;
         const int tap = kk / cpad, c = kk % cpad;
         float v = 0.0f;
         if (o < cout && tap < 27 && c < cin) v = W[(o * cin + c) * 27 + tap];
         Wf[id] = (__bf16)v;
     }
-    if (id < 32 * Kb) {
+    if (Wb != nullptr && id < 32 * Kb) {
         const int c = id / Kb, kk = id % Kb;
         const int tapm = kk / opad, o = kk % opad;
         float v = 0.0f;

@@ -267,14 +267,14 @@ extern "C" int sbli_tgv_init(sbli_ctx* ctx, void* q, const double* phase) {
 // form's scratch exists whenever it is selected (update_table allocates it and
 // a failed allocation leaves the previous variant selected); it is checked
 // again here so that no launch ever runs without it.
-static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
+static int launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int mode, double dt, double A, double B) {
     if (is_staged(ctx, ctx->variant)) {
-        if (!ctx->stg) return;
+        if (!ctx->stg) return fail(ctx, SBLI_ERR_ALLOC, "stage launch: the staged form's scratch is not allocated");
         const bool f64 = ctx->p.dtype == SBLI_F64;
         const StagedArgs a{ctx->stream, f64, ctx->r, f64 ? (const void*)&ctx->c64 : (const void*)&ctx->c32,
                            ctx->stg, mode, dt, A, B, ctx->net ? ctx->clos : nullptr, ctx->net ? ctx->cflag : nullptr};
         staged_launch(a, qin, dq, qout);
-        return;
+        return SBLI_OK;
     }
     const int sym = ctx->p.bc[0] | ctx->p.bc[1] | ctx->p.bc[2];
     const StageArgs a{ctx->stream, ctx->inst_dev, 1, total_wg(ctx), mode, dt, A, B, sym};
@@ -282,6 +282,7 @@ static void launch_any(sbli_ctx* ctx, const void* qin, void* dq, void* qout, int
         StageDispatch<double>::launch(ctx->r, ctx->variant, a, (const double*)qin, (double*)dq, (double*)qout);
     else
         StageDispatch<float>::launch(ctx->r, ctx->variant, a, (const float*)qin, (float*)dq, (float*)qout);
+    return SBLI_OK;
 }
 
 extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
@@ -289,7 +290,8 @@ extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
     if (!q || !rhs) return fail(ctx, SBLI_ERR_ARG, "sbli_rhs: NULL state pointer");
     const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
     if (overlaps(q, rhs, bytes)) return fail(ctx, SBLI_ERR_ARG, "sbli_rhs: q and rhs overlap");
-    launch_any(ctx, q, nullptr, rhs, kModeRHS, 0.0, 0.0, 0.0);
+    const int rc = launch_any(ctx, q, nullptr, rhs, kModeRHS, 0.0, 0.0, 0.0);
+    if (rc != SBLI_OK) return rc;
     HIP_TRY(ctx, hipGetLastError());
     return SBLI_OK;
 }
@@ -298,25 +300,32 @@ extern "C" int sbli_rhs(sbli_ctx* ctx, const void* q, void* rhs) {
 static const double kRK_A[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
 static const double kRK_B[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
 
-// Enqueues nsteps RK3 steps ping-ponging between a and b; returns the buffer
-// that holds the result.
-static void* enqueue_steps(sbli_ctx* ctx, void* a, void* b, void* dq, double dt, int nsteps) {
+// Enqueues nsteps RK3 steps ping-ponging between a and b; *result receives the
+// buffer that holds the result.  Stops at the first failed call.
+static int enqueue_steps(sbli_ctx* ctx, void* a, void* b, void* dq, double dt, int nsteps, void** result) {
     void* src = a;
     void* dst = b;
+    *result = a;
     for (int s = 0; s < nsteps; ++s) {
         for (int k = 0; k < 3; ++k) {
             if (ctx->net) {
-                // closure term of this stage's state, then its guard verdict
-                sbli_net_forward(ctx->net, (const float*)src, 1, ctx->clos);
-                sbli_net_guard(ctx->net, ctx->clos, ctx->cflag, ctx->ccount);
+                // closure term of this stage's state, then its guard verdict (the
+                // network enqueues on its own stream, which attach requires to be
+                // the solver's)
+                int rc = sbli_net_forward(ctx->net, (const float*)src, 1, ctx->clos);
+                if (rc == SBLI_OK) rc = sbli_net_guard(ctx->net, ctx->clos, ctx->cflag, ctx->ccount);
+                if (rc != SBLI_OK)
+                    return fail(ctx, rc, "closure evaluation failed: %s", sbli_net_last_error(ctx->net));
             }
-            launch_any(ctx, src, dq, dst, kModeStage1 + k, dt, kRK_A[k], kRK_B[k]);
+            const int rc = launch_any(ctx, src, dq, dst, kModeStage1 + k, dt, kRK_A[k], kRK_B[k]);
+            if (rc != SBLI_OK) return rc;
             void* t = src;
             src = dst;
             dst = t;
         }
     }
-    return src;
+    *result = src;
+    return SBLI_OK;
 }
 
 extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int nsteps) {
@@ -327,7 +336,9 @@ extern "C" int sbli_rk3_step(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
     const size_t bytes = 5 * (size_t)npoints(ctx) * elem_size(ctx);
     if (overlaps(q, q_tmp, bytes) || overlaps(q, dq, bytes) || overlaps(q_tmp, dq, bytes))
         return fail(ctx, SBLI_ERR_ARG, "sbli_rk3_step: q, q_tmp and dq must not overlap");
-    void* src = enqueue_steps(ctx, q, q_tmp, dq, dt, nsteps);
+    void* src = q;
+    const int rc = enqueue_steps(ctx, q, q_tmp, dq, dt, nsteps, &src);
+    if (rc != SBLI_OK) return rc;
     HIP_TRY(ctx, hipGetLastError());
     if (src != q) HIP_TRY(ctx, hipMemcpyAsync(q, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     return SBLI_OK;
@@ -441,17 +452,19 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
                 (void)hipGetLastError();
                 continue;
             }
-            enqueue_steps(ctx, q, q_tmp, dq, dt, 1);          // warm-up
+            void* res = nullptr;
+            int rc = enqueue_steps(ctx, q, q_tmp, dq, dt, 1, &res);          // warm-up
             hipEventRecord(e0, ctx->stream);
-            enqueue_steps(ctx, q, q_tmp, dq, dt, reps);
+            if (rc == SBLI_OK) rc = enqueue_steps(ctx, q, q_tmp, dq, dt, reps, &res);
             hipEventRecord(e1, ctx->stream);
             hipError_t err = hipEventSynchronize(e1);
-            if (err != hipSuccess) {
+            if (err != hipSuccess || rc != SBLI_OK) {
                 hipEventDestroy(e0);
                 hipEventDestroy(e1);
                 ctx->variant = bv;
                 ctx->zchunk = bz;
                 update_table(ctx);
+                if (rc != SBLI_OK) return rc;
                 return fail(ctx, SBLI_ERR_HIP, "sbli_autotune: %s", hipGetErrorString(err));
             }
             float ms = 0.f;
@@ -821,6 +834,10 @@ extern "C" int sbli_closure_attach(sbli_ctx* ctx, sbli_net* net) {
         if (ctx->p.nx != n || ctx->p.ny != n || ctx->p.nz != n)
             return fail(ctx, SBLI_ERR_ARG, "sbli_closure_attach: grid %dx%dx%d does not match the network's %d^3",
                         ctx->p.nx, ctx->p.ny, ctx->p.nz, n);
+        if (sbli_net_stream(net) != (void*)ctx->stream)
+            return fail(ctx, SBLI_ERR_ARG,
+                        "sbli_closure_attach: the network and the solver must use the same HIP stream "
+                        "(the stage kernel reads the closure term that the network writes)");
         if (!ctx->clos) {
             HIP_TRY(ctx, hipMalloc((void**)&ctx->clos, sizeof(float) * 5 * (size_t)npoints(ctx)));
             HIP_TRY(ctx, hipMalloc((void**)&ctx->cflag, sizeof(int)));

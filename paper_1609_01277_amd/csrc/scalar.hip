@@ -31,6 +31,14 @@ struct ScalarConst {
     double k;                       // diffusivity
 };
 
+// Index of the neighbour m points away on a periodic axis of n points, for any m
+// (a stencil may be wider than the grid: indices wrap modulo n).
+__device__ __forceinline__ int64_t wrapped(int64_t id, int c, int m, int n, int64_t stride) {
+    unsigned flip;
+    const int cc = fold_index(c + m, n, 0, flip);
+    return id + (int64_t)(cc - c) * stride;
+}
+
 // R = -sum_j c_j D_j phi + k sum_j D2_j phi - S, then (MODE != RHS) the 2N stage
 // dq <- A dq + dt R, out <- phi + B dq.  One thread per point; neighbours through
 // the caches (a scalar field needs no LDS staging to stay memory-bound).
@@ -53,8 +61,8 @@ __global__ void __launch_bounds__(256) scalar_stage_kernel(const double* __restr
         if (!c.active[d]) continue;
         double s1 = 0.0, s2 = c.d2c0[d] * f0;
         for (int m = 1; m <= c.r; ++m) {
-            const double fp = phi[shifted(id, coord[d], m, c.n[d], stride[d])];
-            const double fm = phi[shifted(id, coord[d], -m, c.n[d], stride[d])];
+            const double fp = phi[wrapped(id, coord[d], m, c.n[d], stride[d])];
+            const double fm = phi[wrapped(id, coord[d], -m, c.n[d], stride[d])];
             s1 += c.da[d][m - 1] * (fp - fm);
             s2 += c.d2c[d][m - 1] * (fp + fm);
         }
@@ -106,8 +114,6 @@ int make_const(const sbli_scalar_params* p, ScalarConst* c) {
         c->P *= n;
         c->active[d] = n > 1;
         nact += n > 1;
-        if (n > 1 && n < 2 * r + 1)
-            return sfail(SBLI_ERR_ARG, "scalar: n[%d] = %d is below the stencil width %d", d, n, 2 * r + 1);
         if (n > 1 && !(p->length[d] > 0 && std::isfinite(p->length[d])))
             return sfail(SBLI_ERR_ARG, "scalar: length[%d] must be finite and > 0", d);
         const double h = n > 1 ? p->length[d] / n : 1.0;

@@ -21,8 +21,8 @@ def declared_functions():
 
 @pytest.fixture(scope="module")
 def lib():
-    from paper_1609_01277_amd import _lib
-    if not os.path.exists(_lib.LIB_PATH):
+    from paper_1609_01277_amd import _lib, build as libbuild
+    if not libbuild.is_current():
         import __graft_entry__
         __graft_entry__.build()
     return _lib.load()
@@ -84,3 +84,44 @@ def test_init_rejects_bad_dtype_and_null(lib):
     assert lib.sbli_rhs(None, None, None) == sbli.SBLI_ERR_ARG
     assert lib.sbli_rk3_step(None, None, None, None, 0.1, 1) == sbli.SBLI_ERR_ARG
     assert lib.sbli_destroy(None) == sbli.SBLI_OK
+
+
+def test_closure_kernel_exports_validate_arguments(lib):
+    """Shape queries and the argument checks of the per-kernel closure calls.  Every call
+    below fails (or returns) on the host before any device work; the non-NULL pointers
+    are never dereferenced."""
+    from paper_1609_01277_amd import closure
+    import paper_1609_01277_amd as sbli
+    L = closure._L()
+    ERR = sbli.SBLI_ERR_ARG
+    assert [L.sbli_conv3d_cpad(c) for c in (1, 5, 8, 9, 32)] == [8, 8, 8, 32, 32]
+    assert L.sbli_conv3d_cpad(0) == ERR and L.sbli_conv3d_cpad(33) == ERR
+    assert L.sbli_conv3d_packed_width(5) == 224 and L.sbli_conv3d_packed_width(32) == 864
+    assert L.sbli_conv3d_bwd_weight_work_bytes(32) == 4 * (512 * 32 * 864 + 512 * 32)
+    assert L.sbli_conv3d_bwd_weight_work_bytes(5) == 4 * (512 * 32 * 224 + 512 * 32)
+    assert L.sbli_conv3d_bwd_weight_work_bytes(40) == ERR
+    assert L.sbli_mse_grad_work_bytes(64, 4) == 8 * (4 * 64 ** 3 // 256)
+    assert L.sbli_mse_grad_work_bytes(48, 1) == ERR
+    assert L.sbli_net_stream(None) is None
+
+    d = ctypes.c_void_p(0x10000)       # stands for a device pointer; never touched
+
+    def msg():
+        return L.sbli_net_last_error(None).decode()
+
+    assert L.sbli_conv3d_fwd(None, 5, d, d, 32, 64, 1, 1, d, d, None) == ERR
+    assert L.sbli_conv3d_fwd(d, 5, d, d, 32, 48, 1, 1, d, d, None) == ERR and "multiple of 32" in msg()
+    assert L.sbli_conv3d_fwd(d, 5, d, d, 5, 64, 1, closure.ACT_GELU, d, d, None) == ERR and "cout = 32" in msg()
+    assert L.sbli_conv3d_fwd(d, 5, d, d, 32, 64, 1, 7, d, d, None) == ERR and "act" in msg()
+    assert L.sbli_conv3d_fwd(d, 40, d, d, 32, 64, 1, 1, d, d, None) == ERR
+    assert L.sbli_conv3d_fwd(d, 5, d, d, 32, 64, 0, 1, d, d, None) == ERR and "batch" in msg()
+    assert L.sbli_conv3d_pack(d, 5, 32, None, None, None) == ERR
+    assert L.sbli_conv3d_bwd_data(d, 0, d, 64, 1, None, d, None) == ERR
+    assert L.sbli_conv3d_bwd_weight(d, 32, d, 32, 64, 1, d, None, d, 1024, None) == ERR and "work" in msg()
+    assert L.sbli_mse_grad(d, 5, d, d, 64, 1, d, d, d, 1 << 20, None) == ERR and "ystride" in msg()
+    assert L.sbli_mse_grad(d, 8, d, d, 64, 4, d, d, d, 8, None) == ERR and "work" in msg()
+    assert L.sbli_adam_step(d, d, d, d, 10, 1e-3, 0, None) == ERR
+    assert L.sbli_adam_step(d, d, d, d, 10, 0.0, 1, None) == ERR
+    assert L.sbli_adam_step(d, d, d, d, 0, 1e-3, 1, None) == sbli.SBLI_OK
+    assert L.sbli_gelu_bwd(d, d, -1, d, None) == ERR
+    assert L.sbli_gelu_bwd(d, d, 0, d, None) == sbli.SBLI_OK

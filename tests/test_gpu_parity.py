@@ -198,3 +198,44 @@ def test_full_size_sampled_step_parity(oracle_mod, n, order):
     del q, qt, dq
     s.close()
     torch.cuda.empty_cache()
+
+
+TOL32_STEP = 1e-5     # stated FP32 tolerance: relative per field, one step from a shared state
+
+
+@pytest.mark.parametrize("n", [256, 512])
+def test_full_size_sampled_step_fp32(oracle_mod, n):
+    """FP32 form at full size (order 4): one RK3 step of Taylor-Green in the autotuned
+    launch configuration the benchmark times, against the FP64 oracle started from the
+    same FP32-rounded state, at sampled points computed one by one.  What remains is the
+    FP32 rounding of one step: stencil sums of terms up to |rho E u| / h (about 1e4 at
+    512^3) rounded at 6e-8, times dt, plus the rounding of the stored state."""
+    sbli, torch = _sbli()
+    order = 4
+    dt = synth.tgv_dt(n)
+    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
+    print("building oracle TGV state %d^3" % n, flush=True)
+    q32 = oracle.tgv_init(p).astype(np.float32)
+    q0 = q32.astype(np.float64)
+    s = sbli.Solver(n, order=order, dtype="f32", **synth.TGV)
+    tune = s.autotune(reps=2)
+    print("launch configuration", tune, flush=True)
+    q = torch.from_numpy(q32).cuda()
+    del q32
+    qt, dq = s.empty_state(), s.empty_state()
+    s.rk3_step(q, qt, dq, dt, 1)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(n + 32)
+    pts = [(0, 0, 0), (n - 1, n - 1, n - 1), (n // 2, 1, n - 2), (3, n - 4, n // 3)]
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(4)]
+    ref = oracle.rk3_at_points(q0, p, dt, pts)
+    idx = torch.tensor([[z, y, x] for (x, y, z) in pts], device="cuda")
+    got = q[:, idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy().T.astype(np.float64)
+    scale = np.abs(q0).reshape(5, -1).max(axis=1)
+    scale[1:4] = scale[1:4].max()
+    err = (np.abs(got - ref) / scale).max(axis=0)
+    print("FP32 %d^3 one step: relative error per field %s" % (n, err))
+    assert err.max() <= TOL32_STEP, err
+    del q, qt, dq
+    s.close()
+    torch.cuda.empty_cache()
