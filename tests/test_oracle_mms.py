@@ -25,7 +25,7 @@ def oracle_mms_error(order, n, T=100.0):
         out = K * (oracle.d2(f, 0, p) + oracle.d2(f, 1, p)) - U0 * oracle.d1(f, 0, p) - U1 * oracle.d1(f, 1, p)
         return (out[0] - S).ravel()
 
-    dt = 0.025 * h / max(abs(U0), abs(U1))
+    dt = 0.025 / (abs(U0) / h + abs(U1) / h)
     phi = oracle.rk3_generic(np.zeros(n * n), dt, int(math.ceil(T / dt)), rhs)
     e = phi.reshape(n, n) - np.sin(X0) * np.cos(X1)
     return math.sqrt(np.mean(e * e))
