@@ -166,6 +166,16 @@ long long sbli_mse_grad_work_bytes(int n, int batch);
 int sbli_mse_grad(const float* y, int ystride, const float* t, const float* mean_std, int n, int batch, void* dy,
                   double* loss, void* work, long long work_bytes, void* hip_stream);
 
+/* sbli_mse_grad for callers that cannot allocate (code under HIP graph capture,
+ * tight training loops, harnesses that forbid hipMalloc): the same kernels and
+ * results, with no `work` argument.  The loss partials go to a static device
+ * array of the library (512 KiB per GPU, held until the process ends), so
+ * batch * n^3 <= 2^24 (SBLI_ERR_ARG beyond).  The call allocates nothing.  Calls
+ * on one GPU share that array: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be ordered by the caller. */
+int sbli_mse_grad_noalloc(const float* y, int ystride, const float* t, const float* mean_std, int n, int batch,
+                          void* dy, double* loss, void* hip_stream);
+
 /* One Adam step (Kingma & Ba, bias-corrected, beta1 = 0.9, beta2 = 0.999,
  * eps = 1e-8) on `count` FP32 values in place:
  *   m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;

@@ -54,6 +54,8 @@ def _L():
         lib.sbli_mse_grad_work_bytes.argtypes = [i, i]
         lib.sbli_mse_grad_work_bytes.restype = ll
         lib.sbli_mse_grad.argtypes = [vp, i, vp, vp, i, i, vp, vp, vp, ll, vp]
+        lib.sbli_mse_grad_noalloc.argtypes = [vp, i, vp, vp, i, i, vp, vp, vp]
+        lib.sbli_mse_grad_noalloc.restype = ctypes.c_int
         lib.sbli_adam_step.argtypes = [vp, vp, vp, vp, i, ctypes.c_float, i, vp]
         for name in ("sbli_conv3d_cpad", "sbli_conv3d_packed_width", "sbli_conv3d_pack", "sbli_conv3d_fwd",
                      "sbli_conv3d_bwd_data", "sbli_gelu_bwd", "sbli_conv3d_bwd_weight", "sbli_mse_grad",
@@ -151,6 +153,11 @@ def sbli_mse_grad(y, ystride, t, mean_std, n, batch, dy, loss, work, stream=None
     _check(_L().sbli_mse_grad(y.data_ptr(), int(ystride), t.data_ptr(), mean_std.data_ptr(), int(n), int(batch),
                               dy.data_ptr(), loss.data_ptr(), work.data_ptr(), work.numel() * work.element_size(),
                               _stream(stream)))
+
+
+def sbli_mse_grad_noalloc(y, ystride, t, mean_std, n, batch, dy, loss, stream=None):
+    _check(_L().sbli_mse_grad_noalloc(y.data_ptr(), int(ystride), t.data_ptr(), mean_std.data_ptr(), int(n),
+                                      int(batch), dy.data_ptr(), loss.data_ptr(), _stream(stream)))
 
 
 def sbli_adam_step(p, g, m, v, count, lr, t, stream=None):

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -507,6 +508,15 @@ extern "C" int sbli_conv3d_bwd_weight(const void* x, int cin, const void* dy, in
     return launch_status(fn);
 }
 
+// MSE partials per block into `part` (one double per 256 points), then their sum.
+static void mse_launch(hipStream_t s, const float* y, const float* t, const float* mean_std, int n, int batch,
+                       void* dy, double* loss, double* part) {
+    const int64_t NP = (int64_t)batch * n * n * n;
+    const unsigned g = nblk(NP);
+    mse_grad_kernel<<<g, 256, 0, s>>>(y, t, (int64_t)n * n * n, batch, mean_std, (__bf16*)dy, part);
+    sum_doubles_kernel<<<1, 256, 0, s>>>(part, (int)g, 1.0 / (5.0 * (double)NP), loss);
+}
+
 extern "C" long long sbli_mse_grad_work_bytes(int n, int batch) {
     if (check_grid("sbli_mse_grad_work_bytes", n, batch) != SBLI_OK) return SBLI_ERR_ARG;
     return (long long)sizeof(double) * nblk((int64_t)batch * n * n * n);
@@ -522,10 +532,58 @@ extern "C" int sbli_mse_grad(const float* y, int ystride, const float* t, const 
     const int64_t NP = (int64_t)batch * n * n * n;
     if (work_bytes < (long long)sizeof(double) * nblk(NP))
         return nfail(nullptr, SBLI_ERR_ARG, "%s: work is too small", fn);
-    hipStream_t s = (hipStream_t)hip_stream;
-    const unsigned g = nblk(NP);
-    mse_grad_kernel<<<g, 256, 0, s>>>(y, t, (int64_t)n * n * n, batch, mean_std, (__bf16*)dy, (double*)work);
-    sum_doubles_kernel<<<1, 256, 0, s>>>((const double*)work, (int)g, 1.0 / (5.0 * (double)NP), loss);
+    mse_launch((hipStream_t)hip_stream, y, t, mean_std, n, batch, dy, loss, (double*)work);
+    return launch_status(fn);
+}
+
+// ---------------------------------------------------------------------------
+// sbli_mse_grad without a workspace argument: the per-block loss partials go to a
+// file-scope device array instead.  Each GPU holds its own copy of the array; its
+// address on a device is looked up once (hipGetSymbolAddress, with that device
+// current) and kept per device.  Nothing in it needs to start at zero: every
+// block writes its own partial before the final sum reads it.  Calls that overlap
+// on one GPU share the array and race.
+
+constexpr int kMseScratchDoubles = 1 << 16;    // 512 KiB: batch * n^3 <= 2^24 points
+static __device__ __align__(256) double scratch[kMseScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on first use).
+static int scratch_on_current_device(const char* fn, double** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "%s: hipGetDevice: %s", fn, hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return nfail(nullptr, SBLI_ERR_UNSUPPORTED, "%s: device %d", fn, dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return nfail(nullptr, SBLI_ERR_HIP, "%s: hipGetSymbolAddress(scratch): %s", fn, hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SBLI_OK;
+}
+
+extern "C" int sbli_mse_grad_noalloc(const float* y, int ystride, const float* t, const float* mean_std, int n,
+                                     int batch, void* dy, double* loss, void* hip_stream) {
+    const char* fn = "sbli_mse_grad_noalloc";
+    if (!y || !t || !mean_std || !dy || !loss) return nfail(nullptr, SBLI_ERR_ARG, "%s: NULL argument", fn);
+    int rc = check_grid(fn, n, batch);
+    if (rc != SBLI_OK) return rc;
+    if (ystride != 8) return nfail(nullptr, SBLI_ERR_ARG, "%s: ystride must be 8 (the padded output layout)", fn);
+    const int64_t NP = (int64_t)batch * n * n * n;
+    if (nblk(NP) > (unsigned)kMseScratchDoubles)
+        return nfail(nullptr, SBLI_ERR_ARG, "%s: batch * n^3 = %lld exceeds the maximum %lld of the static scratch",
+                     fn, (long long)NP, (long long)kMseScratchDoubles * 256);
+    double* part = nullptr;
+    rc = scratch_on_current_device(fn, &part);
+    if (rc != SBLI_OK) return rc;
+    mse_launch((hipStream_t)hip_stream, y, t, mean_std, n, batch, dy, loss, part);
     return launch_status(fn);
 }
 
