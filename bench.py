@@ -7,8 +7,10 @@ paper's time step for that grid (3.385e-3 at 64^3, halved per doubling).  A step
 is one pass of the whole hot path: three fused residual + RK-update stages over
 the full grid.  The state starts resident in HBM.
 
-Prints ONE JSON line on stdout.  Extra measurements (FP32 state, orders 8 and 12) and the
-CPU oracle baseline are attached to the same line.
+The line's value is the median of three timed runs of --steps steps.  Prints ONE JSON
+line on stdout.  Extra measurements (FP32 state, orders 8 and 12, 256^3, the grid study's
+200-step schedule with diagnostics every 10 steps, the 64-box ensemble and its FP32 error,
+the closure network's kernels) and the CPU oracle baseline are attached to the same line.
 """
 import argparse
 import json
@@ -60,8 +62,9 @@ def counted_traffic(n, order, dtype, tuning):
                      + c["write_kib_per_dispatch"] * c["copy_write_factor"])
 
 
-def measure(sbli, torch, n, order, dtype, steps, warmup):
-    """Time `steps` RK3 steps after `warmup`; returns a dict of results."""
+def measure(sbli, torch, n, order, dtype, steps, warmup, runs=3):
+    """Time `runs` runs of `steps` RK3 steps after `warmup` (HIP events on the solver's
+    stream, state resident in HBM) and keep the median run; returns a dict of results."""
     import synth
     s = sbli.Solver(n, order=order, dtype=dtype, **synth.TGV)
     tune = s.autotune(reps=2)
@@ -72,13 +75,16 @@ def measure(sbli, torch, n, order, dtype, steps, warmup):
     if warmup:
         s.rk3_step(q, qt, dq, dt, warmup)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    s.rk3_step(q, qt, dq, dt, steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
+    times = []
+    for _ in range(runs):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.rk3_step(q, qt, dq, dt, steps)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        times.append(ev0.elapsed_time(ev1))
+    ms = sorted(times)[len(times) // 2]
     diag, code = s.diagnostics(q, check=False)
     P = n ** 3
     word = 8 if dtype == "f64" else 4
@@ -90,10 +96,51 @@ def measure(sbli, torch, n, order, dtype, steps, warmup):
     s.close()
     torch.cuda.empty_cache()
     return dict(n=n, order=order, dtype=dtype, steps=steps, ms=ms, ms_per_step=ms / steps,
-                value=P * steps / (ms * 1e-3) / 1e6, avg_launch_ms=avg_launch_ms,
+                run_ms=times, value=P * steps / (ms * 1e-3) / 1e6, avg_launch_ms=avg_launch_ms,
                 bytes_per_launch=bytes_per_launch, achieved_gbs=achieved,
                 frac=achieved / HBM_PEAK_GBS, diag_status=code, Ek=diag["Ek"],
                 enstrophy=diag["enstrophy"], tuning=tune)
+
+
+def measure_schedule(sbli, torch, n, order, steps=200, every=10):
+    """The Taylor-Green throughput schedule of the paper's grid study at one size and
+    order: `steps` RK3 steps from the initial state with kinetic energy and enstrophy
+    taken every `every` steps (and at the start), timed end to end on the host clock
+    with the diagnostics in it; also the stepping alone (HIP events)."""
+    import synth
+    s = sbli.Solver(n, order=order, dtype="f64", **synth.TGV)
+    s.autotune(reps=2)
+    q, qt, dq = s.empty_state(), s.empty_state(), s.empty_state()
+    dt = synth.tgv_dt(n)
+    stream = torch.cuda.current_stream()
+    s.tgv_init(q)
+    s.rk3_step(q, qt, dq, dt, 1)          # warm-up step, then start again from t = 0
+    s.tgv_init(q)
+    torch.cuda.synchronize()
+    samples = []
+    step_ms = 0.0
+    t0 = time.perf_counter()
+    for k in range(0, steps + 1, every):
+        d, code = s.diagnostics(q, check=False)
+        samples.append((k * dt, d["Ek"], d["enstrophy"]))
+        if k < steps:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            s.rk3_step(q, qt, dq, dt, every)
+            e1.record(stream)
+            e1.synchronize()
+            step_ms += e0.elapsed_time(e1)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    del q, qt, dq
+    s.close()
+    torch.cuda.empty_cache()
+    P = n ** 3
+    return {"n": n, "order": order, "steps": steps, "diagnostics_every": every,
+            "value_with_diagnostics": P * steps / wall / 1e6,
+            "value_stepping_only": P * steps / (step_ms * 1e-3) / 1e6,
+            "wall_s": wall, "stepping_ms": step_ms, "samples_t_Ek_enstrophy": samples,
+            "unit": "Mpoint-RK3-steps/s"}
 
 
 def measure_batch(sbli, torch, steps):
@@ -123,14 +170,28 @@ def measure_batch(sbli, torch, steps):
     ms_seq = e0.elapsed_time(e1)
     diags, code = b.diagnostics(q, check=False)
     v, zmax = b.get_tuning()
+    # error of the FP32 form: the same ensemble and steps from the initial state in
+    # FP32 and in FP64, per-box kinetic energy and enstrophy (FP64 sums of both)
+    b.tgv_init(q)
+    b.step(q, qt, dq, steps)
+    d32, _ = b.diagnostics(q, check=False)
     del q, qt, dq
     b.close()
+    b64 = sbli.Batch(synth.batch_instances(), order=4, dtype="f64")
+    q, qt, dq = b64.tgv_init(b64.empty_state()), b64.empty_state(), b64.empty_state()
+    b64.step(q, qt, dq, steps)
+    d64, _ = b64.diagnostics(q, check=False)
+    del q, qt, dq
+    b64.close()
     torch.cuda.empty_cache()
+    rel = lambda k: max(abs(d32[i][k] - d64[i][k]) / abs(d64[i][k]) for i in range(len(d64)))
     return {"boxes": 64, "points": pts, "steps": steps,
             "graph_value": pts * steps / (ms_graph * 1e-3) / 1e6,
             "sequential_value": pts * steps / (ms_seq * 1e-3) / 1e6,
             "speedup": ms_seq / ms_graph, "graph_ms": ms_graph, "sequential_ms": ms_seq,
-            "unit": "Mpoint-RK3-steps/s", "variant": v, "zmax": zmax, "status": code}
+            "unit": "Mpoint-RK3-steps/s", "variant": v, "zmax": zmax, "status": code,
+            "fp32_vs_fp64_after_steps": {"Ek_max_rel_err": rel(0), "enstrophy_max_rel_err": rel(1),
+                                          "mean_rho_max_rel_err": rel(2), "mean_rhoE_max_rel_err": rel(6)}}
 
 
 def measure_closure(torch, n=64, batch=4, reps=10):
@@ -179,19 +240,47 @@ def measure_closure(torch, n=64, batch=4, reps=10):
             "bf16_dense_peak_tflops": 2500.0, "frac_fwd_bwd": tf_train / 2500.0}
 
 
-def cpu_baseline(n=256, order=4):
-    """The FP64 oracle, as it stands, on the host cores: one RK3 step of TGV n^3."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n=256, steps=3, n1=128):
+    """The FP64 oracle, as it stands, on the host: `steps` RK3 steps of the Taylor-Green
+    state at n^3 on all host threads for orders 4 and 8, and one step at n1^3 on one
+    thread (order 4)."""
     import oracle
     import synth
-    p = oracle.Params(n=(n, n, n), order=order, **synth.TGV)
-    q = oracle.tgv_init(p)
-    t0 = time.perf_counter()
-    oracle.rk3(q, p, synth.tgv_dt(n), 1)
-    t = time.perf_counter() - t0
-    return {"value": n ** 3 / t / 1e6, "unit": "Mpoint-RK3-steps/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "1 RK3 step of the Taylor-Green state at %d^3, order %d, FP64 (whole-array C "
-                      "oracle, OpenMP over z-planes); %.1f s" % (n, order, t)}
+
+    def run(nn, order, k):
+        p = oracle.Params(n=(nn, nn, nn), order=order, **synth.TGV)
+        q = oracle.tgv_init(p)
+        t0 = time.perf_counter()
+        oracle.rk3(q, p, synth.tgv_dt(nn), k)
+        return time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    t4 = run(n, 4, steps)
+    t8 = run(n, 8, steps)
+    oracle.set_num_threads(1)
+    try:
+        t1 = run(n1, 4, 1)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": steps * n ** 3 / t4 / 1e6, "unit": "Mpoint-RK3-steps/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "order8_value": steps * n ** 3 / t8 / 1e6,
+            "single_thread_value": n1 ** 3 / t1 / 1e6,
+            "sample": "whole-array C oracle (FP64, OpenMP over z-planes) on the Taylor-Green state: %d RK3 "
+                      "steps at %d^3 on %d threads, order 4 (%.1f s; value) and order 8 (%.1f s; order8_value); "
+                      "1 step at %d^3, order 4, on 1 thread (%.1f s; single_thread_value)"
+                      % (steps, n, threads, t4, t8, n1, t1)}
 
 
 def main():
@@ -261,10 +350,25 @@ def main():
                                                                     100 * r["frac"]))
 
     if not args.no_extra:
+        for (nn, order) in ((256, 4), (256, 8)):
+            r = measure(sbli, torch, nn, order, "f64", args.steps, args.warmup)
+            key = "f64_order%d_%dcube" % (order, nn)
+            extra[key] = {k: r[k] for k in ("value", "ms_per_step", "achieved_gbs", "frac", "tuning")}
+            log("extra %s: %.1f Mpt-steps/s (%.1f%%)" % (key, r["value"], 100 * r["frac"]))
+        # the grid study's schedule: 200 steps, kinetic energy and enstrophy every 10
+        for (nn, order) in ((512, 4), (512, 8), (256, 4), (256, 8)):
+            r = measure_schedule(sbli, torch, nn, order)
+            extra["schedule_f64_order%d_%dcube" % (order, nn)] = r
+            log("extra schedule %d^3 order %d: %.1f Mpt-steps/s with diagnostics every 10 steps "
+                "(%.1f stepping only)" % (nn, order, r["value_with_diagnostics"], r["value_stepping_only"]))
+
+    if not args.no_extra:
         rb = measure_batch(sbli, torch, 100)
         extra["batched_f32_order4_64boxes"] = rb
-        log("extra batched: graph %.1f vs sequential %.1f Mpt-steps/s (x%.2f)" % (
-            rb["graph_value"], rb["sequential_value"], rb["speedup"]))
+        log("extra batched: graph %.1f vs sequential %.1f Mpt-steps/s (x%.2f); FP32 vs FP64 after 100 "
+            "steps: Ek %.2e, enstrophy %.2e" % (rb["graph_value"], rb["sequential_value"], rb["speedup"],
+                                                 rb["fp32_vs_fp64_after_steps"]["Ek_max_rel_err"],
+                                                 rb["fp32_vs_fp64_after_steps"]["enstrophy_max_rel_err"]))
 
     if not args.no_extra:
         rc = measure_closure(torch)
@@ -274,9 +378,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle, 1 step at %d^3" % args.cpu_n)
-        cpu = cpu_baseline(args.cpu_n, args.order)
-        log("cpu baseline: %.2f Mpt-steps/s on %d threads" % (cpu["value"], cpu["cores"]))
+        log("cpu baseline: oracle, 3 steps at %d^3 (orders 4, 8), 1 step at 128^3 on one thread" % args.cpu_n)
+        cpu = cpu_baseline(args.cpu_n)
+        log("cpu baseline: %.2f Mpt-steps/s on %d threads (%s); order 8 %.2f; one thread %.3f" % (
+            cpu["value"], cpu["cores"], cpu["cpu_model"], cpu["order8_value"], cpu["single_thread_value"]))
 
     word = 8 if args.dtype == "f64" else 4
     line = {
@@ -287,6 +392,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": main_r["ms_per_step"],
+        "timed_runs_ms": main_r["run_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
