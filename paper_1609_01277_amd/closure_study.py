@@ -4,6 +4,10 @@
    3200} to t = 10.  At evenly spaced times the state q_f is box-filtered to 64^3
    (width 4 fine cells), together with its residual: the training pair is
    (F q_f, C* = F R_f(q_f) - R_c(F q_f)), R_c the coarse 64^3 FP32 residual.
+   With --inputs coarse the input is instead the state q_c of the plain coarse
+   solver run alongside from F q_f(0) (one coarse step per `ratio` fine steps), and
+   the target C* = F R_f(q_f) - R_c(q_c): the network is trained on the states a
+   coarse run produces, which are the states it meets once coupled.
 2. Per-field standardisation from the pairs, Adam training of the closure network
    (BF16 MFMA kernels of the library) on the pairs.
 3. A-posteriori: coarse 64^3 FP32 runs (dt 3.385e-3) from F q_f(0) to t = 10 with
@@ -49,6 +53,9 @@ def main(argv=None):
     ap.add_argument("--diag-every", type=int, default=10, help="coarse steps between diagnostics")
     ap.add_argument("--hold-out", type=int, default=10,
                     help="every n-th snapshot is held out of training for the a-priori test")
+    ap.add_argument("--inputs", choices=["filtered", "coarse"], default="filtered",
+                    help="network inputs of the training pairs: the filtered fine state, or the state of "
+                         "the plain coarse solver run alongside")
     args = ap.parse_args(argv)
 
     torch.cuda.set_device(0)
@@ -74,16 +81,27 @@ def main(argv=None):
         fine.tgv_init(q)
         Rf = fine.empty_state()
         fq = torch.empty((5, nc, nc, nc), dtype=torch.float32, device="cuda")
-        snap_steps = sorted(set(int(round(i * steps_f / max(per_re[ri] - 1, 1))) for i in range(per_re[ri])))
+        along = args.inputs == "coarse"
+        if along:
+            # snapshots where a coarse step ends, so both runs are at the same time
+            snap_steps = sorted(set(r * int(round(i * steps_f / r / max(per_re[ri] - 1, 1)))
+                                    for i in range(per_re[ri])))
+            qc, qct, dqc = coarse.empty_state(), coarse.empty_state(), coarse.empty_state()
+            cl.sbli_box_filter(q, nf, 5, r, qc)
+        else:
+            snap_steps = sorted(set(int(round(i * steps_f / max(per_re[ri] - 1, 1))) for i in range(per_re[ri])))
         snap_set = set(snap_steps)
         diag_every_f = args.diag_every * r
         ek, en, times = [], [], []
         for step in range(steps_f + 1):
             if step in snap_set and k < args.snapshots:
-                cl.sbli_box_filter(q, nf, 5, r, X[k])
+                if along:
+                    X[k].copy_(qc)
+                else:
+                    cl.sbli_box_filter(q, nf, 5, r, X[k])
                 fine.rhs(q, Rf)
-                coarse.rhs(X[k], Y[k])                         # R_c(F q_f)
-                cl.sbli_box_filter(Rf, nf, 5, r, Y[k], subtract=True)   # C* = F R_f - R_c(F q_f)
+                coarse.rhs(X[k], Y[k])                         # R_c of the input state
+                cl.sbli_box_filter(Rf, nf, 5, r, Y[k], subtract=True)   # C* = F R_f - R_c(input)
                 k += 1
             if step % diag_every_f == 0:
                 cl.sbli_box_filter(q, nf, 5, r, fq)
@@ -93,9 +111,13 @@ def main(argv=None):
                 times.append(step * dt_f)
             if step < steps_f:
                 fine.rk3_step(q, qt, dq, dt_f, 1)
+                if along and (step + 1) % r == 0:
+                    coarse.rk3_step(qc, qct, dqc, dt_c, 1)
             if step % 2000 == 0:
                 log("Re %g: fine step %d / %d, %d snapshots, %.1f s" % (Re, step, steps_f, k, time.time() - t0))
         ref_diag[Re] = {"t": times, "Ek": ek, "enstrophy": en}
+        if along:
+            del qc, qct, dqc
         del q, qt, dq, Rf
         fine.close()
         coarse.close()

@@ -1,11 +1,16 @@
 """What the trained closure gains over the method without it (small configuration of
 the closure study: 128^3 FP64 fine runs filtered to 32^3, Re 1600, t in [0, 2]).
 
-A-priori: on snapshots held out of training, the network's closure term is closer to
-the filtered-fine target C* = F R_f - R_c(F q_f) than the method without closure
-(which predicts 0, relative error 1).  A-posteriori: the coarse run with the closure
-stays finite, the guard accepts the network's terms, and the filtered kinetic energy
-error against the filtered fine solution is reported next to the plain coarse run's.
+Two ways of making training pairs, each followed by coupled (a-posteriori) coarse runs
+with and without the closure, judged against the filtered fine solution:
+- inputs the filtered fine state F q_f (target F R_f - R_c(F q_f));
+- inputs the state of the plain coarse solver run alongside, q_c (target
+  F R_f - R_c(q_c)): the network then trains on the kind of state it meets when
+  coupled.
+For each: the guard accepts (almost) every evaluation, and the maximum over time of the
+filtered kinetic-energy and enstrophy errors is below the plain coarse run's.  The
+filtered-input network also beats the method without closure a-priori (held-out
+snapshots; relative L2 error of the closure term, 1 without closure).
 """
 import json
 import math
@@ -15,23 +20,33 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-def test_trained_closure_beats_plain_coarse_operator(tmp_path):
+def _run(tmp_path, inputs):
+    from paper_1609_01277_amd import closure_study
+    out = tmp_path / ("closure_small_%s.json" % inputs)
+    closure_study.main(["--nf", "128", "--t-end", "2", "--res", "1600", "--snapshots", "200",
+                        "--epochs", "12", "--hold-out", "10", "--inputs", inputs, "--out", str(out)])
+    return json.loads(out.read_text())
+
+
+@pytest.mark.parametrize("inputs", ["filtered", "coarse"])
+def test_trained_closure_beats_plain_coarse_run(tmp_path, inputs):
     import torch
     if not torch.cuda.is_available():
         pytest.fail("GPU test run without a HIP device")
-    from paper_1609_01277_amd import closure_study
-    out = tmp_path / "closure_small.json"
-    closure_study.main(["--nf", "128", "--t-end", "2", "--res", "1600", "--snapshots", "200",
-                        "--epochs", "12", "--hold-out", "10", "--out", str(out)])
-    d = json.loads(out.read_text())
+    d = _run(tmp_path, inputs)
     ap = d["a_priori"]
-    print("a-priori relative L2 error per field:", ap["rel_l2_err_per_field"], "all:", ap["rel_l2_err_all"])
-    assert ap["held_out_snapshots"] == 20
-    assert ap["rel_l2_err_all"] < 0.9
     post = d["a_posteriori"]["1600.0"]
     plain, clos = post["plain"], post["closure"]
-    print("Ek error max: plain %.4g, closure %.4g" % (plain["Ek_err_max"], clos["Ek_err_max"]))
     acc, rej = clos["guard_accepted_rejected"]
-    assert acc > 0
+    print("inputs %s: a-priori relative L2 error %.4f; a-posteriori max error, plain vs closure: "
+          "Ek %.4g vs %.4g, enstrophy %.4g vs %.4g; guard accepted %d, rejected %d" % (
+              inputs, ap["rel_l2_err_all"], plain["Ek_err_max"], clos["Ek_err_max"],
+              plain["enstrophy_err_max"], clos["enstrophy_err_max"], acc, rej))
     for e in (plain, clos):
         assert all(math.isfinite(v) for v in e["Ek"] + e["enstrophy"])
+    assert acc >= 0.9 * (acc + rej)
+    assert clos["Ek_err_max"] < plain["Ek_err_max"]
+    assert clos["enstrophy_err_max"] < plain["enstrophy_err_max"]
+    if inputs == "filtered":
+        assert ap["held_out_snapshots"] == 20
+        assert ap["rel_l2_err_all"] < 0.5

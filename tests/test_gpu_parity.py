@@ -200,7 +200,11 @@ def test_full_size_sampled_step_parity(oracle_mod, n, order):
     torch.cuda.empty_cache()
 
 
-TOL32_STEP = 1e-5     # stated FP32 tolerance: relative per field, one step from a shared state
+# Stated FP32 tolerance: relative per field, one step from a shared state.  The stored
+# state's own rounding is 6e-8 relative; the momentum update carries dt times the FP32
+# rounding of the pressure-gradient sums (|p| / h ~ 6e3 at 512^3, at 6e-8): ~1e-7 each.
+# Measured: <= 2.2e-7 at 256^3 and 512^3.
+TOL32_STEP = 1e-6
 
 
 @pytest.mark.parametrize("n", [256, 512])
