@@ -432,12 +432,19 @@ __device__ __forceinline__ void fused_stage_body(const T* __restrict__ q, T* __r
                 if (do_out && e1) store_pl();
                 __syncthreads();
             }
-            // 4. residual and RK update at the output plane o = L - 2R.  The global
-            // accesses of this step sit in branches (output lanes, ragged tiles),
-            // and the counter that loads are waited on also counts stores: a path
-            // that skips them is padded with as many dropped stores, so that the
-            // compiler's wait for the next prefetched plane never has to cover
-            // this iteration's stores.
+            // 4. residual and RK update at the output plane o = L - 2R.
+            // The counter a wave waits on for its loads also counts its stores, and
+            // the compiler (stores and loads may complete out of order) waits for it
+            // to reach zero.  The next plane's prefetched state is therefore waited
+            // for here, in every lane, before this plane's stores are issued: they
+            // then drain during the next iteration instead of being waited for at
+            // its start.  The global accesses of this step sit in branches (output
+            // lanes, ragged tiles): a path that skips them is padded with as many
+            // dropped stores, so that every lane's counter stays in step.
+            if constexpr (PRE > 0) {
+                asm volatile("" : "+v"(pq0), "+v"(pq1), "+v"(pq2), "+v"(pq3), "+v"(pq4));
+                asm volatile("" : "+v"(pr0), "+v"(pr1), "+v"(pr2), "+v"(pr3));
+            }
             constexpr int NLD = (MODE == kModeStage2 || MODE == kModeStage3) ? 5 : 0;
             constexpr int NST = (MODE == kModeRHS || MODE == kModeStage3) ? 5 : 10;
             if (do_out && interior) {
