@@ -351,7 +351,7 @@ extern "C" int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]) {
     const double gm1 = ctx->p.gamma - 1.0;
     const int r = ctx->r;
 #define DIAG_LAUNCH(T, RR)                                                                                      \
-    diag_partial_kernel<T, RR><<<nb, kDiagThreads, 0, ctx->stream>>>((const T*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, \
+    diag_partial_kernel<T, RR><<<nb, DiagShape<RR>::NT, 0, ctx->stream>>>((const T*)q, ctx->p.nx, ctx->p.ny, ctx->p.nz, \
                                                                      ctx->diag_da, gm1, ctx->p.bc[0], ctx->p.bc[1], \
                                                                      ctx->p.bc[2], ctx->diag_part)
     if (ctx->p.dtype == SBLI_F64) {
