@@ -8,7 +8,7 @@
 // make_pf from q wherever a point is read; the same function of the same inputs,
 // they are the values the fused kernel keeps in its window.
 //
-//   1. staged_nested_tiled_kernel: nf = (V_0, V_1, V_2, theta - g_00,
+//   1. staged_nested_zring_kernel: nf = (V_0, V_1, V_2, theta - g_00,
 //      theta - g_11, theta - g_22) with g_ij = D_j u_i, V_j = u_i tau_ij (paper
 //      Sec. "Expanding": the inner derivative of a nested term is taken first);
 //   2. staged_tiled_kernel:  the residual (paper eqs. of mass, momentum and
@@ -26,12 +26,13 @@
 
 namespace sbli {
 
-// Both steps run in tiles: a workgroup owns a square tile of (x, y) columns
-// (nested_tile<R>() wide for the nested-field step, kStagedTile for the
-// residual step) and a run of zchunk z-planes (the launches use runs of one plane; see
-// staged_unit).  Per plane it stages what the x/y stencils read into
-// LDS, so every element is loaded once instead of once per neighbour that needs
-// it; the z neighbours of the thread's own column come from memory.
+// Both steps run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
+// (x, y) columns and a run of zchunk z-planes (the residual step runs one plane
+// per workgroup, the nested-field step runs of kNestedRun; see staged_unit).  Per
+// plane it stages what the x/y stencils read into LDS, so every element is
+// loaded once instead of once per neighbour that needs it.  The z neighbours of
+// the thread's own column come from memory in the residual step and from a
+// register ring in the nested-field step.
 //
 // The residual step stages one strip at a time: the tile with its x arms (TS rows
 // of TS + 2R points) for the x sums, then the tile with its y arms (TS + 2R rows of
@@ -41,13 +42,9 @@ namespace sbli {
 // which keeps a workgroup's LDS small enough that registers, not LDS, bound the
 // number of workgroups per CU up to order 12.
 constexpr int kStagedTile = 16;
-// The nested-field step holds three fields per LDS point and few registers, so
-// at R = 6 it takes a larger tile: 32 x 32 (1024 threads, 46 KB of LDS) stages
-// 1.75 points per output point instead of 2.5 with 16 x 16 (order 12: 2,257 ->
-// 2,305-2,345 Mpoint-steps/s at 512^3).  At R = 5 the two tile sizes measure
-// the same, and below it 16 x 16 is as fast or faster.
-template <int R>
-constexpr int nested_tile() { return R >= 6 ? 32 : 16; }
+// Planes per run of the z-marching nested-field step (2R planes of the own
+// column are loaded ahead of each run).
+constexpr int kNestedRun = 64;
 constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
 // The unit of work of a tiled launch is (tile, run of zc planes).  Units are
@@ -223,76 +220,162 @@ __global__ void __launch_bounds__(kStagedTile * kStagedTile)
     }
 }
 
-// The nested-field step: the velocity (u_i = rho u_i / rho, as make_pf forms it) staged.
+// The nested-field step marching in z.  A workgroup owns a tile and a run of
+// zchunk planes, and each thread keeps the velocity of its own column over the
+// planes z-R..z+R in a register ring (2R+1 planes, rotated by unrolling the plane
+// loop 2R+1 times, so every ring index is a compile-time constant).  Per plane
+// only the x and y arms of the tile are loaded (one plane ahead, into
+// registers); the tile's own points are written into LDS from the ring.  Each
+// velocity is formed once per point and plane, as fast_recip(rho) * rho u_i (the
+// values the fused kernel's gradient step reads), and the sums over m run in
+// ascending order per component and axis, as there.  LDS is double-buffered:
+// one barrier per plane.
 template <typename T, int R, int TS>
 __global__ void __launch_bounds__(TS * TS)
-    staged_nested_tiled_kernel(const T* __restrict__ q, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
+    staged_nested_zring_kernel(const T* __restrict__ q, T* __restrict__ nf, const BoxConst<T> c, int tiles_x,
                                int tiles_y, int zchunk) {
-    constexpr int BW = TS + 2 * R;
-    __shared__ T su[3][BW][BW];
+    constexpr int BW = TS + 2 * R, NT = TS * TS, W = 2 * R + 1;
+    constexpr int NARM = 4 * R * TS;                  // arm points of a plane (no corners)
+    constexpr int APT = (NARM + NT - 1) / NT;         // arm points per thread
+    __shared__ T su[2][3][BW][BW];
     const int nx = c.n[0], ny = c.n[1], nz = c.n[2];
     const int64_t P = c.P, plane = (int64_t)nx * ny;
     int tile, chunk;
     if (!staged_unit(tiles_x * tiles_y, (nz + zchunk - 1) / zchunk, tile, chunk)) return;
     const int z0 = chunk * zchunk;
-    const int z1 = min(z0 + zchunk, nz);
+    const int run = min(zchunk, nz - z0);
     const int x0 = (tile % tiles_x) * TS, y0 = (tile / tiles_x) * TS;
     const int tid = threadIdx.x, cx = tid % TS, cy = tid / TS;
     const bool store = x0 + cx < nx && y0 + cy < ny;
-    unsigned fdummy;
-    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fdummy) * nx + fold_index(x0 + cx, nx, c.sym[0], fdummy);
-    for (int z = z0; z < z1; ++z) {
-        const int64_t pz = (int64_t)z * plane;
-        __syncthreads();
-        for (int e = tid; e < BW * BW; e += TS * TS) {
-            const int lx = e % BW, ly = e / BW;
-            if ((lx < R || lx >= R + TS) && (ly < R || ly >= R + TS)) continue;
-            unsigned fx, fy;
-            const int64_t ix = pz + (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], fy) * nx +
-                               fold_index(x0 - R + lx, nx, c.sym[0], fx);
-            const T rr = fast_recip(q[ix]);
-            su[0][ly][lx] = flip_sign(q[P + ix] * rr, fx);
-            su[1][ly][lx] = flip_sign(q[2 * P + ix] * rr, fy);
-            su[2][ly][lx] = q[3 * P + ix] * rr;
+    unsigned fxo, fyo;
+    const int64_t col = (int64_t)fold_index(y0 + cy, ny, c.sym[1], fyo) * nx + fold_index(x0 + cx, nx, c.sym[0], fxo);
+    // this thread's arm points: LDS position and column (with its mirror flags)
+    int aoff[APT];
+    int64_t acol[APT];
+    unsigned afx[APT] = {}, afy[APT] = {};
+#pragma unroll
+    for (int k = 0; k < APT; ++k) {
+        const int a = tid + k * NT;
+        int lx = 0, ly = 0;
+        if (a < NARM) {
+            const int side = a / (R * TS), r = a % (R * TS);
+            if (side < 2) {
+                ly = R + r / R;
+                lx = (side == 0 ? 0 : R + TS) + r % R;
+            } else {
+                lx = R + r % TS;
+                ly = (side == 2 ? 0 : R + TS) + r / TS;
+            }
         }
+        // a thread without this arm point loads its own column instead (unused), so
+        // that every wavefront issues the same loads
+        aoff[k] = a < NARM ? ly * BW + lx : -1;
+        acol[k] = a < NARM ? (int64_t)fold_index(y0 - R + ly, ny, c.sym[1], afy[k]) * nx +
+                                 fold_index(x0 - R + lx, nx, c.sym[0], afx[k])
+                           : col;
+    }
+    // velocity of the own column at plane z (mirrored in z when z lies outside)
+    auto own_u = [&](int z, T (&u)[3]) {
+        unsigned fz;
+        const int64_t id = (int64_t)map_index(z, nz, c.sym[2], fz) * plane + col;
+        const T rr = fast_recip(q[id]);
+        u[0] = q[P + id] * rr;
+        u[1] = q[2 * P + id] * rr;
+        u[2] = flip_sign(q[3 * P + id] * rr, fz);
+    };
+    T ring[W][3];
+#pragma unroll
+    for (int k = 0; k < W; ++k) ring[k][0] = ring[k][1] = ring[k][2] = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * R; ++k) own_u(z0 - R + k, ring[k]);
+    // requested one plane ahead: the own column's entering plane (rho, rho u_i) and
+    // the arms of the next centre plane
+    T pe[4], pa[APT][4];
+    auto issue = [&](int it) {
+        unsigned fz;
+        const int64_t id = (int64_t)map_index(z0 + it + R, nz, c.sym[2], fz) * plane + col;
+        pe[0] = q[id];
+        pe[1] = q[P + id];
+        pe[2] = q[2 * P + id];
+        pe[3] = q[3 * P + id];
+        const int64_t pz = (int64_t)(z0 + it) * plane;
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            const int64_t ix = pz + acol[k];
+            pa[k][0] = q[ix];
+            pa[k][1] = q[P + ix];
+            pa[k][2] = q[2 * P + ix];
+            pa[k][3] = q[3 * P + ix];
+        }
+    };
+    issue(0);
+    auto body = [&](auto ph, const int it) {
+        constexpr int PH = decltype(ph)::value;
+        auto slot = [](int k) { return (k + PH) % W; };
+        const int z = z0 + it;
+        const int b = it & 1;
+        // the entering plane z + R joins the ring; plane z's arms and tile go to LDS
+        {
+            unsigned fz;
+            map_index(z + R, nz, c.sym[2], fz);
+            const T rr = fast_recip(pe[0]);
+            ring[slot(2 * R)][0] = pe[1] * rr;
+            ring[slot(2 * R)][1] = pe[2] * rr;
+            ring[slot(2 * R)][2] = flip_sign(pe[3] * rr, fz);
+        }
+#pragma unroll
+        for (int k = 0; k < APT; ++k) {
+            if (aoff[k] >= 0) {
+                const T rr = fast_recip(pa[k][0]);
+                T* s0 = &su[b][0][0][0];
+                s0[aoff[k]] = flip_sign(pa[k][1] * rr, afx[k]);
+                s0[BW * BW + aoff[k]] = flip_sign(pa[k][2] * rr, afy[k]);
+                s0[2 * BW * BW + aoff[k]] = pa[k][3] * rr;
+            }
+        }
+        const T (&uc)[3] = ring[slot(R)];
+        su[b][0][R + cy][R + cx] = flip_sign(uc[0], fxo);
+        su[b][1][R + cy][R + cx] = flip_sign(uc[1], fyo);
+        su[b][2][R + cy][R + cx] = uc[2];
+        if (it + 1 < run) issue(it + 1);
         __syncthreads();
         const int ly = R + cy, lx = R + cx;
-        // offset by offset, all three components: each z neighbour's density and
-        // its reciprocal are loaded and formed once (every sum still runs over m
-        // in ascending order)
         T g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-#pragma unroll 1
+#pragma unroll
         for (int m = 1; m <= R; ++m) {
-            unsigned fp, fm;
-            const int64_t ip = (int64_t)map_index(z + m, nz, c.sym[2], fp) * plane + col;
-            const int64_t im = (int64_t)map_index(z - m, nz, c.sym[2], fm) * plane + col;
-            const T rp = fast_recip(q[ip]), rm = fast_recip(q[im]);
 #pragma unroll
-            for (int b = 0; b < 3; ++b) {
-                g[b][0] = fmaT(c.da[0][m - 1], su[b][ly][lx + m] - su[b][ly][lx - m], g[b][0]);
-                g[b][1] = fmaT(c.da[1][m - 1], su[b][ly + m][lx] - su[b][ly - m][lx], g[b][1]);
-                T up = q[(b + 1) * P + ip] * rp, um = q[(b + 1) * P + im] * rm;
-                if (b == 2) { up = flip_sign(up, fp); um = flip_sign(um, fm); }
-                g[b][2] = fmaT(c.da[2][m - 1], up - um, g[b][2]);
+            for (int bb = 0; bb < 3; ++bb) {
+                g[bb][0] = fmaT(c.da[0][m - 1], su[b][bb][ly][lx + m] - su[b][bb][ly][lx - m], g[bb][0]);
+                g[bb][1] = fmaT(c.da[1][m - 1], su[b][bb][ly + m][lx] - su[b][bb][ly - m][lx], g[bb][1]);
+                g[bb][2] = fmaT(c.da[2][m - 1], ring[slot(R + m)][bb] - ring[slot(R - m)][bb], g[bb][2]);
             }
         }
-        if (!store) continue;
-        const int64_t id = pz + col;
-        const T rc = fast_recip(q[id]);
-        const T uc[3] = {q[P + id] * rc, q[2 * P + id] * rc, q[3 * P + id] * rc};
-        const T theta = g[0][0] + g[1][1] + g[2][2];
+        if (store) {
+            const int64_t id = (int64_t)z * plane + col;
+            const T theta = g[0][0] + g[1][1] + g[2][2];
 #pragma unroll
-        for (int jj = 0; jj < 3; ++jj) {
-            T v = 0;
+            for (int jj = 0; jj < 3; ++jj) {
+                T v = 0;
 #pragma unroll
-            for (int ii = 0; ii < 3; ++ii) {
-                T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
-                if (ii == jj) tau = fmaT(-c.inv_Re23, theta, tau);
-                v = fmaT(uc[ii], tau, v);
+                for (int ii = 0; ii < 3; ++ii) {
+                    T tau = c.inv_Re * (g[ii][jj] + g[jj][ii]);
+                    if (ii == jj) tau = fmaT(-c.inv_Re23, theta, tau);
+                    v = fmaT(uc[ii], tau, v);
+                }
+                __builtin_nontemporal_store(v, &nf[jj * P + id]);
+                __builtin_nontemporal_store(theta - g[jj][jj], &nf[(3 + jj) * P + id]);
             }
-            __builtin_nontemporal_store(v, &nf[jj * P + id]);
-            __builtin_nontemporal_store(theta - g[jj][jj], &nf[(3 + jj) * P + id]);
+        } else {
+            // as many (dropped) stores, so that waiting for the next plane's loads
+            // never has to cover this plane's stores
+            dropped_stores<6>(nf);
         }
+    };
+    for (int it0 = 0; it0 < run; it0 += W) {
+        static_for<W>([&](auto ph) {
+            const int it = it0 + decltype(ph)::value;
+            if (it < run) body(ph, it);
+        });
     }
 }
 

@@ -8,21 +8,22 @@ namespace sbli {
 template <typename T, int R>
 static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* nf) {
     const BoxConst<T>& c = *(const BoxConst<T>*)a.box;
-    const int zc = 1;   // one plane per workgroup: see staged_unit
-    auto grid_of = [&](int tiles) {
+    auto grid_of = [&](int tiles, int zc) {
         const int64_t units = (int64_t)tiles * ((c.n[2] + zc - 1) / zc);
         return (unsigned)(kStagedXcds * ((units + kStagedXcds - 1) / kStagedXcds));
     };
     {
-        constexpr int TN = nested_tile<R>();
+        constexpr int TN = kStagedTile;
         const int tx = (c.n[0] + TN - 1) / TN, ty = (c.n[1] + TN - 1) / TN;
-        staged_nested_tiled_kernel<T, R, TN><<<grid_of(tx * ty), TN * TN, 0, a.stream>>>(qin, nf, c, tx, ty, zc);
+        const int zn = kNestedRun;
+        staged_nested_zring_kernel<T, R, TN><<<grid_of(tx * ty, zn), TN * TN, 0, a.stream>>>(qin, nf, c, tx, ty, zn);
     }
     const int tx = (c.n[0] + kStagedTile - 1) / kStagedTile, ty = (c.n[1] + kStagedTile - 1) / kStagedTile;
-    const unsigned grid = grid_of(tx * ty);
     constexpr int NT = kStagedTile * kStagedTile;
     const T dt = (T)a.dt, A = (T)a.A, B = (T)a.B;
     const T* clos = (const T*)a.clos;
+    const int zc = 1;   // one plane per workgroup: see staged_unit
+    const unsigned grid = grid_of(tx * ty, zc);
     switch (a.mode) {
         case kModeRHS:
             staged_tiled_kernel<T, R, kModeRHS><<<grid, NT, 0, a.stream>>>(qin, nf, dq, qout, c, dt, A, B, clos,
