@@ -370,3 +370,30 @@ def test_attach_rejects_a_network_on_another_stream():
     closure.attach(s, None)
     net2.close()
     s.close()
+
+
+def test_weight_gradient_at_96_cube_matches_oracle():
+    """dW and db at 96^3, batch 1, 5 -> 8 channels: a grid that is not a power of
+    two, so each of the weight-gradient kernel's 512 workgroups takes 54 blocks of 32
+    points (not a whole number of 3-block x-rows), with 8 of the 32 output rows live."""
+    closure, torch = _mods()
+    n, cin, cout = 96, 5, 8
+    P = n ** 3
+    rng = np.random.default_rng(96)
+    x = np.zeros((1, P, 8), dtype=np.float32)
+    x[..., :cin] = bf16(rng.standard_normal((1, P, cin)))
+    d = np.zeros((1, P, 8), dtype=np.float32)
+    d[..., :cout] = bf16(rng.standard_normal((1, P, cout)))
+    cu = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(torch.bfloat16).cuda()
+    work = torch.empty(closure.sbli_conv3d_bwd_weight_work_bytes(cin) // 4, device="cuda")
+    dW = torch.empty((cout, cin, 27), device="cuda")
+    db = torch.empty(cout, device="cuda")
+    closure.sbli_conv3d_bwd_weight(cu(x), cin, cu(d), cout, n, 1, dW, db, work)
+    torch.cuda.synchronize()
+    pl = lambda a, c: a.reshape(1, n, n, n, -1)[..., :c].transpose(0, 4, 1, 2, 3).astype(np.float64)
+    xs, ds = pl(x, cin), pl(d, cout)
+    rW, rb = nn.conv3d_bwd_weight(xs, ds)
+    aW, ab = nn.conv3d_bwd_weight(np.abs(xs), np.abs(ds))
+    # per workgroup 54 blocks x 2 MFMA steps of 16 products, then 512 partials in four chains
+    _check_sum(to_host(dW).reshape(cout, cin, 3, 3, 3), rW, aW, 2 * 54 * 16 + 130, "dW")
+    _check_sum(to_host(db), rb, ab, 128 + 256 + 64 + 8, "db")
