@@ -160,12 +160,12 @@ def test_diagnostics_flag_nonfinite_and_negative(oracle_mod):
             s.diagnostics(to_dev(torch, q))
 
 
-FULL = [(256, 4), (256, 8), (512, 4), (512, 8)]
+FULL = [(256, 4), (256, 8), (512, 4), (512, 8), (256, 12), (512, 12)]
 
 
 @pytest.mark.parametrize("n,order", FULL)
 def test_full_size_sampled_step_parity(oracle_mod, n, order):
-    """Full-size Taylor-Green (256^3, 512^3; orders 4, 8), FP64, one RK3 step with the
+    """Full-size Taylor-Green (256^3, 512^3; orders 4, 8, 12), FP64, one RK3 step with the
     paper's dt, through the same entry point and in the same autotuned launch
     configuration the benchmark times; sampled points are computed one by one by the
     oracle.  Conservation sums must not drift."""
