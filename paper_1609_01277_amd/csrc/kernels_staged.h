@@ -43,7 +43,8 @@ namespace sbli {
 // number of workgroups per CU up to order 12.
 constexpr int kStagedTile = 16;
 // Planes per run of the z-marching nested-field step (2R planes of the own
-// column are loaded ahead of each run).
+// column are loaded ahead of each run).  Runs of 32 and 128 measure the same at
+// 512^3, orders 8 and 12.
 constexpr int kNestedRun = 64;
 constexpr int kStagedFields = 12;   // rho, rho u_i, rho E, u_i, p, T, then V_d, theta - g_dd of the axis d
 
