@@ -79,7 +79,9 @@ typedef struct sbli_ctx sbli_ctx;
  */
 int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out);
 
-/* Release a context and its scratch; waits for its stream first.  NULL is a no-op. */
+/* Release a context and its scratch; waits for its stream first.  NULL is a no-op.
+ * Everything is released even when a HIP call fails; the first failure is then
+ * returned (SBLI_ERR_HIP, message from sbli_last_error(NULL)). */
 int sbli_destroy(sbli_ctx* ctx);
 
 /* Message of the last failed call on `ctx` (or of the last failed sbli_init when
@@ -212,6 +214,9 @@ typedef struct sbli_instance {
 typedef struct sbli_batch sbli_batch;
 
 int sbli_batch_init(const sbli_instance* inst, int count, int order, int dtype, void* hip_stream, sbli_batch** out);
+/* Release an ensemble (its graph, table and per-box contexts) after waiting for
+ * its stream; everything is released even when a call fails, and the first
+ * failure is returned (message from sbli_batch_last_error(NULL)). */
 int sbli_batch_destroy(sbli_batch* b);
 const char* sbli_batch_last_error(const sbli_batch* b);
 int sbli_batch_layout(const sbli_batch* b, size_t* offsets);

@@ -36,6 +36,9 @@ typedef struct sbli_net sbli_net;
  * workspaces for up to max_batch samples.  Parameters start at zero and the
  * statistics at mean 0 / std 1 with no guard limit. */
 int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net** out);
+/* Release a network: waits for its stream, frees every buffer even when a HIP
+ * call fails, and returns the first failure (SBLI_ERR_HIP, message from
+ * sbli_net_last_error(NULL)).  NULL is a no-op. */
 int sbli_net_destroy(sbli_net* net);
 const char* sbli_net_last_error(const sbli_net* net);
 int sbli_net_num_params(const sbli_net* net);

@@ -78,16 +78,22 @@ extern "C" const char* sbli_net_last_error(const sbli_net* net) { return net ? n
 
 extern "C" int sbli_net_destroy(sbli_net* net) {
     if (!net) return SBLI_OK;
-    hipStreamSynchronize(net->stream);
+    // everything is released whatever fails; the first failure is reported
+    hipError_t first = hipStreamSynchronize(net->stream);
+    auto release = [&](void* p) {
+        const hipError_t e = hipFree(p);
+        if (first == hipSuccess) first = e;
+    };
     for (int l = 0; l < kNetLayers; ++l) {
-        hipFree(net->L[l].Wf);
-        hipFree(net->L[l].Wb);
+        release(net->L[l].Wf);
+        release(net->L[l].Wb);
     }
     void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->stats, net->x, net->h1, net->h2,
                     net->dy, net->d2, net->d1, net->pre1, net->pre2, net->y, net->wpart, net->bpart, net->loss_part,
                     net->loss};
-    for (void* p : ptrs) hipFree(p);
+    for (void* p : ptrs) release(p);
     delete net;
+    if (first != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "sbli_net_destroy: %s", hipGetErrorString(first));
     return SBLI_OK;
 }
 

@@ -214,11 +214,12 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
     if (e != hipSuccess) {
         int code = (e == hipErrorOutOfMemory) ? SBLI_ERR_ALLOC : SBLI_ERR_HIP;
         fail(nullptr, code, "sbli_init: %s", hipGetErrorString(e));
-        hipFree(x->diag_part);
-        hipFree(x->diag_da);
-        hipFree(x->diag_out);
-        hipFree(x->inst_dev);
-        hipFree(x->stg);
+        // cleanup after the reported failure: its own status adds nothing
+        (void)hipFree(x->diag_part);
+        (void)hipFree(x->diag_da);
+        (void)hipFree(x->diag_out);
+        (void)hipFree(x->inst_dev);
+        (void)hipFree(x->stg);
         delete x;
         return code;
     }
@@ -228,16 +229,15 @@ extern "C" int sbli_init(const sbli_params* p, void* hip_stream, sbli_ctx** out)
 
 extern "C" int sbli_destroy(sbli_ctx* ctx) {
     if (!ctx) return SBLI_OK;
-    hipStreamSynchronize(ctx->stream);
-    hipFree(ctx->diag_part);
-    hipFree(ctx->diag_da);
-    hipFree(ctx->diag_out);
-    hipFree(ctx->inst_dev);
-    hipFree(ctx->stg);
-    hipFree(ctx->clos);
-    hipFree(ctx->cflag);
-    hipFree(ctx->ccount);
+    // everything is released whatever fails; the first failure is reported
+    hipError_t first = hipStreamSynchronize(ctx->stream);
+    for (void* p : {(void*)ctx->diag_part, (void*)ctx->diag_da, (void*)ctx->diag_out, (void*)ctx->inst_dev, ctx->stg,
+                    (void*)ctx->clos, (void*)ctx->cflag, (void*)ctx->ccount}) {
+        const hipError_t e = hipFree(p);
+        if (first == hipSuccess) first = e;
+    }
     delete ctx;
+    if (first != hipSuccess) return fail(nullptr, SBLI_ERR_HIP, "sbli_destroy: %s", hipGetErrorString(first));
     return SBLI_OK;
 }
 
@@ -410,7 +410,7 @@ extern "C" int sbli_set_tuning(sbli_ctx* ctx, int variant, int zchunk) {
     if (e != hipSuccess) {
         ctx->variant = old_v;
         ctx->zchunk = old_z;
-        update_table(ctx);
+        (void)update_table(ctx);   // the previous configuration, rebuilt after the reported failure
         return fail(ctx, e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP, "sbli_set_tuning: %s",
                     hipGetErrorString(e));
     }
@@ -454,21 +454,22 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
             }
             void* res = nullptr;
             int rc = enqueue_steps(ctx, q, q_tmp, dq, dt, 1, &res);          // warm-up
-            hipEventRecord(e0, ctx->stream);
-            if (rc == SBLI_OK) rc = enqueue_steps(ctx, q, q_tmp, dq, dt, reps, &res);
-            hipEventRecord(e1, ctx->stream);
-            hipError_t err = hipEventSynchronize(e1);
+            hipError_t err = hipEventRecord(e0, ctx->stream);
+            if (rc == SBLI_OK && err == hipSuccess) rc = enqueue_steps(ctx, q, q_tmp, dq, dt, reps, &res);
+            if (err == hipSuccess) err = hipEventRecord(e1, ctx->stream);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess && rc == SBLI_OK) err = hipEventElapsedTime(&ms, e0, e1);
             if (err != hipSuccess || rc != SBLI_OK) {
-                hipEventDestroy(e0);
-                hipEventDestroy(e1);
+                // cleanup after the failure reported below
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
                 ctx->variant = bv;
                 ctx->zchunk = bz;
-                update_table(ctx);
+                (void)update_table(ctx);
                 if (rc != SBLI_OK) return rc;
                 return fail(ctx, SBLI_ERR_HIP, "sbli_autotune: %s", hipGetErrorString(err));
             }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
             if (ms < best) {
                 best = ms;
                 bv = v;
@@ -476,11 +477,11 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
     ctx->variant = bv;
     ctx->zchunk = bz;
     HIP_TRY(ctx, update_table(ctx));
+    HIP_TRY(ctx, d0 != hipSuccess ? d0 : d1);
     if (best_ms) *best_ms = best / reps;
     return SBLI_OK;
 }
@@ -534,11 +535,17 @@ static int bfail(sbli_batch* b, int code, const char* fmt, ...) {
 
 static size_t belem(const sbli_batch* b) { return b->dtype == SBLI_F32 ? sizeof(float) : sizeof(double); }
 
-static void batch_drop_graph(sbli_batch* b) {
-    if (b->exec) hipGraphExecDestroy(b->exec);
-    if (b->graph) hipGraphDestroy(b->graph);
+// Releases the captured graph; returns the first failure of the two releases.
+static hipError_t batch_drop_graph(sbli_batch* b) {
+    hipError_t e = hipSuccess;
+    if (b->exec) e = hipGraphExecDestroy(b->exec);
+    if (b->graph) {
+        const hipError_t e2 = hipGraphDestroy(b->graph);
+        if (e == hipSuccess) e = e2;
+    }
     b->exec = nullptr;
     b->graph = nullptr;
+    return e;
 }
 
 // Rebuilds the launch table for the current variant and z-chunk cap, copies it
@@ -573,7 +580,7 @@ static int batch_build_table(sbli_batch* b) {
     const size_t bytes = b->dtype == SBLI_F64 ? sizeof(BoxInst<double>) * b->count : sizeof(BoxInst<float>) * b->count;
     BHIP_TRY(b, hipMemcpyAsync(b->table_dev, src, bytes, hipMemcpyHostToDevice, b->stream));
     BHIP_TRY(b, hipStreamSynchronize(b->stream));
-    batch_drop_graph(b);
+    BHIP_TRY(b, batch_drop_graph(b));
     return SBLI_OK;
 }
 
@@ -613,12 +620,22 @@ static int batch_check_buffers(sbli_batch* b, const char* who, void* q, void* q_
 
 extern "C" int sbli_batch_destroy(sbli_batch* b) {
     if (!b) return SBLI_OK;
-    if (b->stream || b->ctx.size()) hipStreamSynchronize(b->stream);
-    batch_drop_graph(b);
-    if (b->cap) hipStreamDestroy(b->cap);
-    hipFree(b->table_dev);
-    for (sbli_ctx* c : b->ctx) sbli_destroy(c);
+    // everything is released whatever fails; the first failure is reported
+    hipError_t first = hipStreamSynchronize(b->stream);
+    auto keep = [&](hipError_t e) {
+        if (first == hipSuccess) first = e;
+    };
+    keep(batch_drop_graph(b));
+    if (b->cap) keep(hipStreamDestroy(b->cap));
+    keep(hipFree(b->table_dev));
+    int rc = SBLI_OK;
+    for (sbli_ctx* c : b->ctx) {
+        const int r = sbli_destroy(c);
+        if (rc == SBLI_OK) rc = r;
+    }
     delete b;
+    if (first != hipSuccess) return bfail(nullptr, SBLI_ERR_HIP, "sbli_batch_destroy: %s", hipGetErrorString(first));
+    if (rc != SBLI_OK) return bfail(nullptr, rc, "sbli_batch_destroy: %s", sbli_last_error(nullptr));
     return SBLI_OK;
 }
 
@@ -719,21 +736,21 @@ extern "C" int sbli_batch_capture(sbli_batch* b, void* q, void* q_tmp, void* dq,
     int rc = batch_check_buffers(b, "sbli_batch_capture", q, q_tmp, dq);
     if (rc != SBLI_OK) return rc;
     if (nsteps < 1) return bfail(b, SBLI_ERR_ARG, "sbli_batch_capture: nsteps must be >= 1");
-    batch_drop_graph(b);
+    BHIP_TRY(b, batch_drop_graph(b));
     BHIP_TRY(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     batch_enqueue(b, b->cap, q, q_tmp, dq, nsteps);
     hipError_t le = hipGetLastError();
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(b->cap, &g);
     if (le != hipSuccess || ce != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);   // cleanup after the failure reported here
         return bfail(b, SBLI_ERR_HIP, "sbli_batch_capture: %s",
                      hipGetErrorString(le != hipSuccess ? le : ce));
     }
     b->graph = g;
     hipError_t ie = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
     if (ie != hipSuccess) {
-        batch_drop_graph(b);
+        (void)batch_drop_graph(b);   // cleanup after the failure reported here
         return bfail(b, SBLI_ERR_HIP, "sbli_batch_capture: hipGraphInstantiate: %s", hipGetErrorString(ie));
     }
     return SBLI_OK;
@@ -799,23 +816,24 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
             rc = batch_build_table(b);
             if (rc != SBLI_OK) break;
             batch_enqueue(b, b->stream, q, q_tmp, dq, 1);
-            hipEventRecord(e0, b->stream);
-            batch_enqueue(b, b->stream, q, q_tmp, dq, reps);
-            hipEventRecord(e1, b->stream);
-            if (hipEventSynchronize(e1) != hipSuccess) {
+            hipError_t err = hipEventRecord(e0, b->stream);
+            if (err == hipSuccess) batch_enqueue(b, b->stream, q, q_tmp, dq, reps);
+            if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) {
                 rc = SBLI_ERR_HIP;
                 break;
             }
-            float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
             if (ms < best) {
                 best = ms;
                 bv = v;
                 bz = zc[zi];
             }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
+    if (rc == SBLI_OK && (d0 != hipSuccess || d1 != hipSuccess)) rc = SBLI_ERR_HIP;
     b->variant = bv;
     b->zmax = bz;
     int rc2 = batch_build_table(b);
