@@ -9,7 +9,12 @@
    the target C* = F R_f(q_f) - R_c(q_c): the network is trained on the states a
    coarse run produces, which are the states it meets once coupled.
 2. Per-field standardisation from the pairs, Adam training of the closure network
-   (BF16 MFMA kernels of the library) on the pairs.
+   (BF16 MFMA kernels of the library) on the pairs.  With --aggregate K (coarse
+   inputs), K more rounds follow: the fine and coarse runs are repeated with the
+   trained closure coupled into the coarse run, the pairs (q_cc, F R_f(q_f) -
+   R_c(q_cc)) are collected at the states that coupled run visits (R_c the plain
+   coarse residual), and training continues on all pairs so far (dataset
+   aggregation: the network learns the states its own feedback produces).
 3. A-posteriori: coarse 64^3 FP32 runs (dt 3.385e-3) from F q_f(0) to t = 10 with
    and without the closure; filtered kinetic energy and enstrophy against those of
    F q_f(t) (the filtered fine solution is the reference for the error).
@@ -56,7 +61,13 @@ def main(argv=None):
     ap.add_argument("--inputs", choices=["filtered", "coarse"], default="filtered",
                     help="network inputs of the training pairs: the filtered fine state, or the state of "
                          "the plain coarse solver run alongside")
+    ap.add_argument("--aggregate", type=int, default=0,
+                    help="rounds of dataset aggregation (coarse inputs only): pairs from the closure-coupled "
+                         "coarse run, then more training on all pairs")
+    ap.add_argument("--aggregate-epochs", type=int, default=4, help="training epochs after each aggregation round")
     args = ap.parse_args(argv)
+    if args.aggregate and args.inputs != "coarse":
+        ap.error("--aggregate needs --inputs coarse")
 
     torch.cuda.set_device(0)
     nf, r = args.nf, args.ratio
@@ -67,61 +78,77 @@ def main(argv=None):
     res = [float(v) for v in args.res.split(",")]
     steps_f = int(round(args.t_end / dt_f))
     per_re = [args.snapshots // len(res) + (1 if i < args.snapshots % len(res) else 0) for i in range(len(res))]
-    X = torch.empty((args.snapshots, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
+    nrounds = 1 + args.aggregate
+    X = torch.empty((args.snapshots * nrounds, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
     Y = torch.empty_like(X)
     out = {"config": vars(args), "nf": nf, "nc": nc, "dt_fine": dt_f, "dt_coarse": dt_c, "fine_steps": steps_f}
     ref_diag = {}
-    k = 0
     t0 = time.time()
-    for ri, Re in enumerate(res):
-        fine = Solver(nf, order=4, dtype="f64", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
-        fine.autotune()
-        coarse = Solver(nc, order=4, dtype="f32", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
-        q, qt, dq = fine.empty_state(), fine.empty_state(), fine.empty_state()
-        fine.tgv_init(q)
-        Rf = fine.empty_state()
-        fq = torch.empty((5, nc, nc, nc), dtype=torch.float32, device="cuda")
-        along = args.inputs == "coarse"
-        if along:
-            # snapshots where a coarse step ends, so both runs are at the same time
-            snap_steps = sorted(set(r * int(round(i * steps_f / r / max(per_re[ri] - 1, 1)))
-                                    for i in range(per_re[ri])))
-            qc, qct, dqc = coarse.empty_state(), coarse.empty_state(), coarse.empty_state()
-            cl.sbli_box_filter(q, nf, 5, r, qc)
-        else:
-            snap_steps = sorted(set(int(round(i * steps_f / max(per_re[ri] - 1, 1))) for i in range(per_re[ri])))
-        snap_set = set(snap_steps)
-        diag_every_f = args.diag_every * r
-        ek, en, times = [], [], []
-        for step in range(steps_f + 1):
-            if step in snap_set and k < args.snapshots:
-                if along:
-                    X[k].copy_(qc)
-                else:
-                    cl.sbli_box_filter(q, nf, 5, r, X[k])
-                fine.rhs(q, Rf)
-                coarse.rhs(X[k], Y[k])                         # R_c of the input state
-                cl.sbli_box_filter(Rf, nf, 5, r, Y[k], subtract=True)   # C* = F R_f - R_c(input)
-                k += 1
-            if step % diag_every_f == 0:
-                cl.sbli_box_filter(q, nf, 5, r, fq)
-                d, _ = coarse.diagnostics(fq, check=False)
-                ek.append(d["Ek"])
-                en.append(d["enstrophy"])
-                times.append(step * dt_f)
-            if step < steps_f:
-                fine.rk3_step(q, qt, dq, dt_f, 1)
-                if along and (step + 1) % r == 0:
-                    coarse.rk3_step(qc, qct, dqc, dt_c, 1)
-            if step % 2000 == 0:
-                log("Re %g: fine step %d / %d, %d snapshots, %.1f s" % (Re, step, steps_f, k, time.time() - t0))
-        ref_diag[Re] = {"t": times, "Ek": ek, "enstrophy": en}
-        if along:
-            del qc, qct, dqc
-        del q, qt, dq, Rf
-        fine.close()
-        coarse.close()
-        torch.cuda.empty_cache()
+
+    def collect(k, net=None):
+        """Fine runs at every Re with a coarse run alongside (coupled to `net` when
+        given); pairs from index k on.  Returns the next free index."""
+        k_end = k + args.snapshots
+        for ri, Re in enumerate(res):
+            fine = Solver(nf, order=4, dtype="f64", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+            fine.autotune()
+            coarse = Solver(nc, order=4, dtype="f32", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4)
+            plain = Solver(nc, order=4, dtype="f32", Re=Re, Mach=0.1, Pr=0.71, gamma=1.4) if net else coarse
+            q, qt, dq = fine.empty_state(), fine.empty_state(), fine.empty_state()
+            fine.tgv_init(q)
+            Rf = fine.empty_state()
+            fq = torch.empty((5, nc, nc, nc), dtype=torch.float32, device="cuda")
+            along = args.inputs == "coarse"
+            if along:
+                # snapshots where a coarse step ends, so both runs are at the same time
+                snap_steps = sorted(set(r * int(round(i * steps_f / r / max(per_re[ri] - 1, 1)))
+                                        for i in range(per_re[ri])))
+                qc, qct, dqc = coarse.empty_state(), coarse.empty_state(), coarse.empty_state()
+                cl.sbli_box_filter(q, nf, 5, r, qc)
+                if net is not None:
+                    cl.attach(coarse, net)
+            else:
+                snap_steps = sorted(set(int(round(i * steps_f / max(per_re[ri] - 1, 1))) for i in range(per_re[ri])))
+            snap_set = set(snap_steps)
+            diag_every_f = args.diag_every * r
+            ek, en, times = [], [], []
+            for step in range(steps_f + 1):
+                if step in snap_set and k < k_end:
+                    if along:
+                        X[k].copy_(qc)
+                    else:
+                        cl.sbli_box_filter(q, nf, 5, r, X[k])
+                    fine.rhs(q, Rf)
+                    plain.rhs(X[k], Y[k])                          # plain R_c of the input state
+                    cl.sbli_box_filter(Rf, nf, 5, r, Y[k], subtract=True)   # C* = F R_f - R_c(input)
+                    k += 1
+                if net is None and step % diag_every_f == 0:
+                    cl.sbli_box_filter(q, nf, 5, r, fq)
+                    d, _ = coarse.diagnostics(fq, check=False)
+                    ek.append(d["Ek"])
+                    en.append(d["enstrophy"])
+                    times.append(step * dt_f)
+                if step < steps_f:
+                    fine.rk3_step(q, qt, dq, dt_f, 1)
+                    if along and (step + 1) % r == 0:
+                        coarse.rk3_step(qc, qct, dqc, dt_c, 1)
+                if step % 2000 == 0:
+                    log("Re %g: fine step %d / %d, %d snapshots, %.1f s" % (Re, step, steps_f, k, time.time() - t0))
+            if net is None:
+                ref_diag[Re] = {"t": times, "Ek": ek, "enstrophy": en}
+            if along:
+                if net is not None:
+                    cl.attach(coarse, None)
+                del qc, qct, dqc
+            del q, qt, dq, Rf
+            fine.close()
+            coarse.close()
+            if net is not None:
+                plain.close()
+            torch.cuda.empty_cache()
+        return k
+
+    k = collect(0)
     out["data_seconds"] = time.time() - t0
     nsnap = k
     out["snapshots"] = nsnap
@@ -138,31 +165,56 @@ def main(argv=None):
     rng = np.random.default_rng(args.seed)
     xb = torch.empty((args.batch, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
     yb = torch.empty_like(xb)
-    losses = []
     held = np.arange(0, nsnap, args.hold_out) if args.hold_out > 0 else np.zeros(0, dtype=int)
-    train_idx = np.setdiff1d(np.arange(nsnap), held)
-    steps_per_epoch = len(train_idx) // args.batch
     flop_per_sample = 2 * Pc * 27 * (8 * 32 + 32 * 32 + 32 * 32) * 3   # fwd + bwd-data + bwd-weight, padded
+
+    def train(train_idx, epochs):
+        losses = []
+        steps_per_epoch = len(train_idx) // args.batch
+        for ep in range(epochs):
+            perm = train_idx[rng.permutation(len(train_idx))]
+            tot = 0.0
+            for s_ in range(steps_per_epoch):
+                idx = perm[s_ * args.batch:(s_ + 1) * args.batch]
+                for j, i in enumerate(idx):
+                    xb[j].copy_(X[int(i)])
+                    yb[j].copy_(Y[int(i)])
+                tot += net.train_step(xb, yb, args.lr)
+            losses.append(tot / steps_per_epoch)
+            log("epoch %d: mean loss %.5f (%.1f s)" % (ep, losses[-1], time.time() - t1))
+        return losses, epochs * steps_per_epoch
+
+    train_idx = np.setdiff1d(np.arange(nsnap), held)
     t1 = time.time()
     torch.cuda.synchronize()
-    for ep in range(args.epochs):
-        perm = train_idx[rng.permutation(len(train_idx))]
-        tot = 0.0
-        for s in range(steps_per_epoch):
-            idx = perm[s * args.batch:(s + 1) * args.batch]
-            for j, i in enumerate(idx):
-                xb[j].copy_(X[int(i)])
-                yb[j].copy_(Y[int(i)])
-            tot += net.train_step(xb, yb, args.lr)
-        losses.append(tot / steps_per_epoch)
-        log("epoch %d: mean loss %.5f (%.1f s)" % (ep, losses[-1], time.time() - t1))
+    losses, nsteps_train = train(train_idx, args.epochs)
     torch.cuda.synchronize()
     train_s = time.time() - t1
-    nsteps_train = args.epochs * steps_per_epoch
     out["training"] = {"epoch_loss": losses, "seconds": train_s, "steps": nsteps_train,
                        "ms_per_step": 1e3 * train_s / max(nsteps_train, 1),
                        "padded_tflops_per_s": flop_per_sample * args.batch * nsteps_train / train_s / 1e12,
                        "note": "wall time per step includes host-side batch assembly and the loss read-back"}
+    # dataset aggregation: pairs at the states of the closure-coupled coarse run
+    rounds = []
+    for rd in range(args.aggregate):
+        k0 = k
+        k = collect(k, net)
+        agg_idx = np.concatenate([train_idx, np.arange(nsnap, k)])
+        t1 = time.time()
+        l_, n_ = train(agg_idx, args.aggregate_epochs)
+        torch.cuda.synchronize()
+        rounds.append({"pairs_added": int(k - k0), "pairs_total": int(len(agg_idx)), "epoch_loss": l_,
+                       "seconds": time.time() - t1})
+        log("aggregation round %d: %d pairs added, %d in training" % (rd + 1, k - k0, len(agg_idx)))
+    if rounds:
+        # the guard limits follow the pairs trained on (the standardisation stays)
+        net.channel_stats(Y[:k], 1)
+        st_all = net.get_stats()
+        st[20:25] = args.guard * st_all[30:35]
+        st[30:35] = st_all[30:35]
+        net.set_stats(st)
+        out["aggregation"] = rounds
+        out["stats_after_aggregation"] = [float(v) for v in st]
     # time the network kernels alone on one batch (no host work in the loop)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
