@@ -143,6 +143,27 @@ def test_diagnostics_match_oracle(oracle_mod, order):
             assert _diag_close(vals[k], ref[k], scale), (k, vals[k], ref[k])
 
 
+@pytest.mark.parametrize("order", [2, 4, 8, 10, 12])
+def test_diagnostics_random_state_ragged_grid_match_oracle(oracle_mod, order):
+    """Diagnostics of a random state on a 26 x 41 x 35 periodic grid: ragged last tiles in x
+    and y for both tile heights of the diagnostics kernel (16 rows up to order 6, 8 rows
+    above: a last tile of 1 or 9 rows), and a last z-chunk of 3 planes."""
+    sbli, torch = _sbli()
+    n = (26, 41, 35)
+    p = oracle.Params(n=n, order=order, **synth.TGV)
+    s = sbli.Solver(n, order=order, **synth.TGV)
+    q = synth.random_conservative_state(n, seed=40 + order)
+    ref, flags = oracle.diagnostics(q, p)
+    assert flags == (0, 0, 0)
+    got, code = s.diagnostics(to_dev(torch, q))
+    assert code == sbli.SBLI_OK
+    vals = list(got.values())
+    for k in range(7):
+        scale = 1.0 if k != 6 else 180.0
+        assert _diag_close(vals[k], ref[k], scale), (k, vals[k], ref[k])
+    s.close()
+
+
 def test_diagnostics_flag_nonfinite_and_negative(oracle_mod):
     sbli, torch = _sbli()
     n = 24
