@@ -37,10 +37,12 @@ def rel_err(got, ref):
             for f in range(5)]
 
 
-# (70, 40, 26) spans 3 x 2 tiles of the 32 x 32 nested-field step used at order 12
-# (and 5 x 3 of the 16 x 16 residual step), so tile pairs cross tile rows and the
-# ragged last tiles hold mirrored or wrapped columns.
-@pytest.mark.parametrize("order,n", [(10, (26, 27, 29)), (12, (26, 27, 29)), (12, (70, 40, 26))])
+# (70, 40, 26) spans 5 x 3 of the 16 x 16 tiles of both steps, so tile pairs cross tile
+# rows and the ragged last tiles hold mirrored or wrapped columns.  With nz = 100 the
+# z-marching nested-field step runs 64 planes and then 36 (a run starting inside the
+# box, and a short last run).
+@pytest.mark.parametrize("order,n", [(10, (26, 27, 29)), (12, (26, 27, 29)), (12, (70, 40, 26)),
+                                     (10, (26, 27, 100)), (12, (26, 27, 100))])
 def test_high_order_rhs_matches_oracle(order, n):
     sbli, torch = _sbli()
     q0 = synth.random_conservative_state(n, seed=40 + order, mom=0.3)
