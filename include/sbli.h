@@ -35,7 +35,7 @@ extern "C" {
 #define SBLI_ERR_HIP (-2)         /* a HIP runtime call failed                        */
 #define SBLI_ERR_NONFINITE (-3)   /* diagnostics found NaN/Inf, rho <= 0 or p <= 0    */
 #define SBLI_ERR_ALLOC (-4)       /* device or host allocation failed                 */
-#define SBLI_ERR_UNSUPPORTED (-5) /* a valid request this build does not implement    */
+#define SBLI_ERR_UNSUPPORTED (-5) /* a valid request the library does not implement  */
 
 #define SBLI_F64 0
 #define SBLI_F32 1
