@@ -31,7 +31,8 @@ struct StageVariant {
     X(16, 16, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0) X(16, 16, 1, 1, 1, 1, 0)
 #define SBLI_VARIANTS_F2(X)                                                                                   \
     X(16, 8, 1, 0, 1, 0, 0) X(16, 8, 1, 1, 1, 0, 0) X(16, 16, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 1, 0, 0) X(32, 8, 1, 1, 3, 0, 0) \
-    X(16, 16, 1, 1, 3, 0, 0) X(16, 16, 1, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 1, 0) X(16, 16, 1, 1, 3, 1, 0)
+    X(16, 16, 1, 1, 3, 0, 0) X(16, 16, 1, 1, 1, 1, 0) X(32, 8, 1, 1, 1, 1, 0) X(16, 16, 1, 1, 3, 1, 0)            \
+    X(32, 16, 1, 1, 1, 0, 0) X(32, 16, 1, 1, 1, 1, 0)
 #define SBLI_VARIANTS_F3(X) X(16, 16, 0, 0, 1, 0, 0) X(16, 16, 1, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0)
 #define SBLI_VARIANTS_F4(X) X(16, 8, 0, 0, 1, 0, 0) X(16, 8, 1, 0, 1, 0, 0) X(16, 4, 1, 0, 1, 0, 0)
 
