@@ -163,8 +163,10 @@ int sbli_diagnostics(sbli_ctx* ctx, const void* q, double out[7]);
  *   (SBLI_ERR_ALLOC if that fails; the previous selection then stays).
  * sbli_autotune: time every variant with several zchunks (hipEvents on the
  *   context's stream, `reps` RK3 steps each after one warm-up step) using the
- *   caller's device buffers, then select the fastest; *best_ms (may be NULL)
- *   receives its time per step.  The contents of q, q_tmp and dq afterwards are
+ *   caller's device buffers, then select the fastest (a later candidate replaces
+ *   the best so far only when more than 1 % faster, so near-ties resolve to the
+ *   earlier variant and the longer zchunk); *best_ms (may be NULL) receives the
+ *   selected candidate's time per step.  The contents of q, q_tmp and dq afterwards are
  *   unspecified (they are advanced in time).  Synchronises the stream.
  */
 int sbli_num_variants(const sbli_ctx* ctx);

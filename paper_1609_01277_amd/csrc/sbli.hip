@@ -424,6 +424,10 @@ extern "C" int sbli_get_tuning(const sbli_ctx* ctx, int* variant, int* zchunk) {
     return SBLI_OK;
 }
 
+// A later candidate replaces the best one only when it is faster by more than 1 %: candidates
+// within timing noise of each other then resolve to the same (earlier) choice on every run.
+constexpr float kTuneMargin = 0.99f;
+
 extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, double dt, int reps, double* best_ms) {
     if (!ctx) return fail(nullptr, SBLI_ERR_ARG, "sbli_autotune: ctx is NULL");
     if (!q || !q_tmp || !dq) return fail(ctx, SBLI_ERR_ARG, "sbli_autotune: NULL state pointer");
@@ -470,7 +474,7 @@ extern "C" int sbli_autotune(sbli_ctx* ctx, void* q, void* q_tmp, void* dq, doub
                 if (rc != SBLI_OK) return rc;
                 return fail(ctx, SBLI_ERR_HIP, "sbli_autotune: %s", hipGetErrorString(err));
             }
-            if (ms < best) {
+            if (ms < best * kTuneMargin) {
                 best = ms;
                 bv = v;
                 bz = cands[ci];
@@ -826,7 +830,7 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
                 rc = SBLI_ERR_HIP;
                 break;
             }
-            if (ms < best) {
+            if (ms < best * kTuneMargin) {
                 best = ms;
                 bv = v;
                 bz = zc[zi];

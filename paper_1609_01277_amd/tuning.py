@@ -15,6 +15,13 @@ DEFAULT_CACHE = os.environ.get("SBLI_TUNING_CACHE",
                                os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
 
 
+def device_tag(torch):
+    """Architecture and compute-unit count of the current device.  The marketing name is not
+    used: it depends on the host's amdgpu.ids table and on tools loaded into the process."""
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return "%s/%dcu" % (getattr(p, "gcnArchName", "") or p.name, p.multi_processor_count)
+
+
 def cache_key(params, device_name):
     return "%dx%dx%d|order%d|%s|%s" % (params.nx, params.ny, params.nz, params.order,
                                        "f64" if params.dtype == _lib.SBLI_F64 else "f32", device_name)
@@ -42,8 +49,7 @@ def store_cache(entries, path=DEFAULT_CACHE):
 def autotune(solver, reps=2, path=DEFAULT_CACHE, force=False):
     """Select the launch configuration of `solver` (a Solver); returns the cache entry."""
     torch = solver.torch
-    dev = torch.cuda.get_device_name()
-    key = cache_key(solver.params, dev)
+    key = cache_key(solver.params, device_tag(torch))
     cache = load_cache(path)
     ent = cache.get(key)
     nv = _lib.sbli_num_variants(solver.ctx)

@@ -37,3 +37,33 @@ def test_store_then_load_round_trip_leaves_no_temporary(tmp_path):
 
 def test_store_into_missing_directory_fails_quietly(tmp_path):
     assert tuning.store_cache({}, str(tmp_path / "no" / "such" / "dir" / "c.json")) is False
+
+
+class _FakeProps:
+    def __init__(self, arch, name, cus):
+        self.gcnArchName, self.name, self.multi_processor_count = arch, name, cus
+
+
+class _FakeCuda:
+    def __init__(self, props):
+        self._props = props
+
+    def current_device(self):
+        return 0
+
+    def get_device_properties(self, i):
+        return self._props
+
+
+class _FakeTorch:
+    def __init__(self, props):
+        self.cuda = _FakeCuda(props)
+
+
+def test_device_tag_uses_architecture_and_cu_count_not_marketing_name():
+    # the marketing name differs between processes on one machine (it comes from a host table
+    # that may be missing), so two processes must agree on the tag whatever the name reads
+    a = tuning.device_tag(_FakeTorch(_FakeProps("gfx950:sramecc+:xnack-", "", 256)))
+    b = tuning.device_tag(_FakeTorch(_FakeProps("gfx950:sramecc+:xnack-", "AMD Radeon Graphics", 256)))
+    assert a == b == "gfx950:sramecc+:xnack-/256cu"
+    assert tuning.device_tag(_FakeTorch(_FakeProps("", "dev", 8))) == "dev/8cu"
