@@ -813,23 +813,26 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
     BHIP_TRY(b, hipEventCreate(&e1));
     float best = 1e30f;
     int bv = b->variant, bz = b->zmax;
-    for (int v = 0; v < nv; ++v)
+    hipError_t err = hipSuccess;
+    // a failure ends both loops; rc and err then hold it
+    for (int v = 0; v < nv && rc == SBLI_OK && err == hipSuccess; ++v)
         for (int zi = 0; zi < 4; ++zi) {
             b->variant = v;
             b->zmax = zc[zi];
             rc = batch_build_table(b);
             if (rc != SBLI_OK) break;
             batch_enqueue(b, b->stream, q, q_tmp, dq, 1);
-            hipError_t err = hipEventRecord(e0, b->stream);
-            if (err == hipSuccess) batch_enqueue(b, b->stream, q, q_tmp, dq, reps);
+            err = hipGetLastError();
+            if (err == hipSuccess) err = hipEventRecord(e0, b->stream);
+            if (err == hipSuccess) {
+                batch_enqueue(b, b->stream, q, q_tmp, dq, reps);
+                err = hipGetLastError();
+            }
             if (err == hipSuccess) err = hipEventRecord(e1, b->stream);
             if (err == hipSuccess) err = hipEventSynchronize(e1);
             float ms = 0.f;
             if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-            if (err != hipSuccess) {
-                rc = SBLI_ERR_HIP;
-                break;
-            }
+            if (err != hipSuccess) break;
             if (ms < best * kTuneMargin) {
                 best = ms;
                 bv = v;
@@ -837,11 +840,12 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
             }
         }
     const hipError_t d0 = hipEventDestroy(e0), d1 = hipEventDestroy(e1);
-    if (rc == SBLI_OK && (d0 != hipSuccess || d1 != hipSuccess)) rc = SBLI_ERR_HIP;
+    if (err == hipSuccess) err = d0 != hipSuccess ? d0 : d1;
     b->variant = bv;
     b->zmax = bz;
-    int rc2 = batch_build_table(b);
-    if (rc != SBLI_OK) return bfail(b, rc, "sbli_batch_autotune: a timing run failed");
+    const int rc2 = batch_build_table(b);
+    if (rc != SBLI_OK) return rc;   // batch_build_table has recorded the message
+    if (err != hipSuccess) return bfail(b, SBLI_ERR_HIP, "sbli_batch_autotune: %s", hipGetErrorString(err));
     if (rc2 != SBLI_OK) return rc2;
     if (best_ms) *best_ms = best / reps;
     return SBLI_OK;

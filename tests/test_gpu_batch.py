@@ -145,3 +145,24 @@ def test_fp32_ensemble_diagnostics_against_fp64_ensemble():
     print("FP32 vs FP64 ensemble, worst relative error per diagnostic:", worst)
     assert worst[0] <= 1e-5 and worst[1] <= 1e-5, worst
     assert worst[2:].max() <= 1e-6, worst
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_autotune_selects_a_valid_tuning_and_keeps_results(dtype):
+    # the search times every fused variant at zmax 128, 64, 32 and 16 and keeps one; every
+    # variant does the same arithmetic, so stepping after the search is bitwise what it was
+    sbli, torch = _sbli()
+    insts = small_ensemble(count=3, seed=5)
+    b = sbli.Batch(insts, order=4, dtype=dtype)
+    q0 = b.tgv_init(b.empty_state())
+    ref = q0.clone()
+    b.step(ref, b.empty_state(), b.empty_state(), 2)
+    ms = b.autotune(reps=1)
+    assert 0.0 < ms < 1e4
+    v, zmax = b.get_tuning()
+    assert zmax in (128, 64, 32, 16)
+    b.set_tuning(v, zmax)            # the selection is one the library accepts
+    got = q0.clone()
+    b.step(got, b.empty_state(), b.empty_state(), 2)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
