@@ -323,10 +323,17 @@ def main():
         n = args.calibrate_copy * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(5):
             dst.copy_(src)
+        e1.record()
         torch.cuda.synchronize()
-        log("copied %d MiB x 5" % args.calibrate_copy)
+        ms = e0.elapsed_time(e1) / 5
+        # bytes read plus bytes written per copy, over its average duration
+        log("copied %d MiB x 5: %.3f ms per copy, %.0f GB/s read + write" % (
+            args.calibrate_copy, ms, 2 * n * 8 / (ms * 1e-3) / 1e9))
         return
     from paper_1609_01277_amd import build as libbuild
     if not libbuild.is_current():
