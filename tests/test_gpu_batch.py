@@ -166,3 +166,22 @@ def test_batch_autotune_selects_a_valid_tuning_and_keeps_results(dtype):
     b.step(got, b.empty_state(), b.empty_state(), 2)
     torch.cuda.synchronize()
     assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("sizes,count", [((9,), 1), ((9, 17, 40), 6)])
+def test_degenerate_ensembles_equal_sequential_bitwise(sizes, count):
+    # one box alone, and boxes of the smallest order-4 grid (9^3) mixed with larger ones,
+    # under every fused variant: the ensemble launch equals box-by-box stepping bitwise
+    sbli, torch = _sbli()
+    insts = synth.batch_instances(count=count, seed=21, sizes=sizes)
+    b = sbli.Batch(insts, order=4, dtype="f64")
+    q0 = b.tgv_init(b.empty_state())
+    ref = q0.clone()
+    b.step_sequential(ref, b.empty_state(), b.empty_state(), 2)
+    nv = len(sbli.Solver(9, order=4).variants()) - 1      # the fused variants (the batch has no staged form)
+    for v in range(nv):
+        for zmax in (1, 128):
+            b.set_tuning(v, zmax)
+            q = q0.clone()
+            b.step(q, b.empty_state(), b.empty_state(), 2)
+            assert torch.equal(q, ref), (v, zmax)
