@@ -65,6 +65,10 @@ def main(argv=None):
                     help="rounds of dataset aggregation (coarse inputs only): pairs from the closure-coupled "
                          "coarse run, then more training on all pairs")
     ap.add_argument("--aggregate-epochs", type=int, default=4, help="training epochs after each aggregation round")
+    ap.add_argument("--noise", type=float, default=0.0,
+                    help="input-noise injection: every training input is perturbed by Gaussian noise of this many "
+                         "times its field's training-set standard deviation (the target stays that of the clean "
+                         "input), so the network meets states off the training trajectories")
     args = ap.parse_args(argv)
     if args.aggregate and args.inputs != "coarse":
         ap.error("--aggregate needs --inputs coarse")
@@ -166,6 +170,9 @@ def main(argv=None):
     xb = torch.empty((args.batch, 5, nc, nc, nc), dtype=torch.float32, device="cuda")
     yb = torch.empty_like(xb)
     held = np.arange(0, nsnap, args.hold_out) if args.hold_out > 0 else np.zeros(0, dtype=int)
+    noise_scale = torch.tensor(args.noise * st[5:10], dtype=torch.float32, device="cuda").view(1, 5, 1, 1, 1)
+    noise_gen = torch.Generator(device="cuda")
+    noise_gen.manual_seed(args.seed)
     flop_per_sample = 2 * Pc * 27 * (8 * 32 + 32 * 32 + 32 * 32) * 3   # fwd + bwd-data + bwd-weight, padded
 
     def train(train_idx, epochs):
@@ -179,6 +186,8 @@ def main(argv=None):
                 for j, i in enumerate(idx):
                     xb[j].copy_(X[int(i)])
                     yb[j].copy_(Y[int(i)])
+                if args.noise > 0:
+                    xb.add_(torch.randn(xb.shape, device="cuda", generator=noise_gen) * noise_scale)
                 tot += net.train_step(xb, yb, args.lr)
             losses.append(tot / steps_per_epoch)
             log("epoch %d: mean loss %.5f (%.1f s)" % (ep, losses[-1], time.time() - t1))
