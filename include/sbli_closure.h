@@ -64,8 +64,17 @@ int sbli_net_set_stats(sbli_net* net, const float* host_stats);
 int sbli_net_get_stats(sbli_net* net, float* host_stats);
 int sbli_net_channel_stats(sbli_net* net, const float* data, int count, int which);
 
-/* out = destandardised network output for `batch` planar samples q. */
+/* out = destandardised network output for `batch` planar samples q.  In the
+ * conservative mode (sbli_net_set_conservative) each output field of each
+ * sample then has its box mean removed (FP64 sums in a fixed order), so that
+ * the closure term adds nothing to the totals of mass, momentum and energy,
+ * as the exact term F R_f - R_c(F q_f) does (both residuals are in the
+ * conservative form of Sec. "3D Taylor-Green vortex"; the filter keeps totals). */
 int sbli_net_forward(sbli_net* net, const float* q, int batch, float* out);
+/* Conservative mode of sbli_net_forward (and so of the closure term a solver
+ * adds through sbli_closure_attach): on = 1 removes the box means, 0 (the
+ * default) leaves the output as computed.  SBLI_ERR_ARG for other values. */
+int sbli_net_set_conservative(sbli_net* net, int on);
 /* Forward, mean-squared error against the standardised `target` (planar, raw
  * units), backward; gradients stay on the device (sbli_net_get_grads).
  * *loss (host, may be NULL) receives the loss; then the stream is synchronised. */

@@ -7,8 +7,8 @@ no blocking, fusion or reordering, layouts planar [batch][channel][z][y][x].
 
 Pins (tests/test_oracle_nn.py): the convolution against scipy.ndimage.correlate with
 periodic wrap, every hand-derived gradient against central finite differences in
-FP64, Adam's first step against its closed form, and the filter's transfer function
-on Fourier modes.
+FP64, Adam's first step against its closed form, the filter's transfer function
+on Fourier modes, and the box-mean removal on constant and zero-mean fields.
 """
 import math
 
@@ -143,6 +143,15 @@ def forward(params, x):
         cache.append((h, pre))
         h = gelu(pre) if li < len(params) - 1 else pre
     return h, cache
+
+
+def remove_box_mean(y):
+    """Conservative form of a closure term: each field of each sample, planar
+    [batch][field][z][y][x], minus its mean over the box.  The exact closure term
+    F R_f - R_c(F q_f) has zero box mean, because both residuals are in conservative
+    form (paper Sec. "3D Taylor-Green vortex") and the filter keeps totals."""
+    y = np.asarray(y, dtype=np.float64)
+    return y - y.mean(axis=(2, 3, 4), keepdims=True)
 
 
 def mse(y, t):

@@ -33,6 +33,7 @@ def _L():
         lib.sbli_net_get_stats.argtypes = [vp, fp]
         lib.sbli_net_channel_stats.argtypes = [vp, vp, ctypes.c_int, ctypes.c_int]
         lib.sbli_net_forward.argtypes = [vp, vp, ctypes.c_int, vp]
+        lib.sbli_net_set_conservative.argtypes = [vp, ctypes.c_int]
         lib.sbli_net_gradients.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         lib.sbli_net_train_step.argtypes = [vp, vp, vp, ctypes.c_int, ctypes.c_float,
                                             ctypes.POINTER(ctypes.c_double)]
@@ -230,6 +231,10 @@ class ClosureNet:
             out = self.torch.empty_like(q)
         _check(_L().sbli_net_forward(self.net, q.data_ptr(), int(batch), out.data_ptr()), self.net)
         return out
+
+    def set_conservative(self, on=True):
+        """Remove each output field's box mean in forward (and in the closure term)."""
+        _check(_L().sbli_net_set_conservative(self.net, int(bool(on))), self.net)
 
     def gradients(self, q, target):
         loss = ctypes.c_double()

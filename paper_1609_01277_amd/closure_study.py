@@ -69,6 +69,9 @@ def main(argv=None):
                     help="input-noise injection: every training input is perturbed by Gaussian noise of this many "
                          "times its field's training-set standard deviation (the target stays that of the clean "
                          "input), so the network meets states off the training trajectories")
+    ap.add_argument("--conservative", action="store_true",
+                    help="after training, remove the box mean of every field of the closure term (the exact "
+                         "term has none), so the coupled run keeps the totals of mass, momentum and energy")
     args = ap.parse_args(argv)
     if args.aggregate and args.inputs != "coarse":
         ap.error("--aggregate needs --inputs coarse")
@@ -203,6 +206,8 @@ def main(argv=None):
                        "ms_per_step": 1e3 * train_s / max(nsteps_train, 1),
                        "padded_tflops_per_s": flop_per_sample * args.batch * nsteps_train / train_s / 1e12,
                        "note": "wall time per step includes host-side batch assembly and the loss read-back"}
+    if args.conservative:
+        net.set_conservative(True)
     # dataset aggregation: pairs at the states of the closure-coupled coarse run
     rounds = []
     for rd in range(args.aggregate):
@@ -272,8 +277,9 @@ def main(argv=None):
             if mode == "closure":
                 cl.attach(s, net)
             qt, dq = s.empty_state(), s.empty_state()
-            ek, en = [], []
+            ek, en, mass, energy = [], [], [], []
             ratio = []          # per diagnostic step: per-field max |C| / guard limit
+            cmean = []          # per diagnostic step: per-field |box mean of C| / max |C|
             limit = torch.tensor(st[20:25], dtype=torch.float32, device="cuda")
             t2 = time.time()
             for step in range(steps_c + 1):
@@ -281,9 +287,13 @@ def main(argv=None):
                     d, code = s.diagnostics(q, check=False)
                     ek.append(d["Ek"])
                     en.append(d["enstrophy"])
+                    mass.append(d["rho"])
+                    energy.append(d["rhoE"])
                     if mode == "closure":
                         net.forward(q[None], pred)
-                        ratio.append((pred[0].abs().reshape(5, -1).amax(dim=1) / limit).cpu().tolist())
+                        amax = pred[0].abs().reshape(5, -1).amax(dim=1)
+                        ratio.append((amax / limit).cpu().tolist())
+                        cmean.append((pred[0].double().reshape(5, -1).mean(dim=1).abs() / amax.double()).cpu().tolist())
                 if step < steps_c:
                     s.rk3_step(q, qt, dq, dt_c, 1)
             torch.cuda.synchronize()
@@ -293,11 +303,15 @@ def main(argv=None):
             e_en = np.abs(np.array(en[:m]) - np.array(refd["enstrophy"][:m])) / np.max(np.abs(refd["enstrophy"][:m]))
             entry = {"Ek_err_max": float(e_ek.max()), "Ek_err_rms": float(math.sqrt(np.mean(e_ek ** 2))),
                      "enstrophy_err_max": float(e_en.max()), "enstrophy_err_rms": float(math.sqrt(np.mean(e_en ** 2))),
+                     # largest relative change of the box totals of mass and total energy over the run
+                     "mass_drift_max": float(np.max(np.abs(np.array(mass) / mass[0] - 1.0))),
+                     "energy_drift_max": float(np.max(np.abs(np.array(energy) / energy[0] - 1.0))),
                      "seconds": time.time() - t2, "Ek": ek, "enstrophy": en}
             if mode == "closure":
                 entry["guard_accepted_rejected"] = list(cl.counts(s))
                 r_ = np.array(ratio)
                 entry["guard_ratio_max_per_field"] = r_.max(axis=0).tolist()
+                entry["closure_mean_over_max_per_field"] = np.array(cmean).max(axis=0).tolist()
                 over = np.nonzero(r_.max(axis=1) > 1.0)[0]
                 entry["guard_first_exceed_t"] = float(over[0] * args.diag_every * dt_c) if len(over) else None
                 log("Re %g closure: guard accepted %d rejected %d; max |C|/limit per field %s; first exceeded at t = %s" % (
@@ -305,9 +319,9 @@ def main(argv=None):
                     np.array2string(r_.max(axis=0), precision=3), entry["guard_first_exceed_t"]))
                 cl.attach(s, None)
             res_run[mode] = entry
-            log("Re %g %s: Ek err max %.4f rms %.4f; enstrophy err max %.4f rms %.4f" % (
+            log("Re %g %s: Ek err max %.4f rms %.4f; enstrophy err max %.4f rms %.4f; mass drift %.2e, energy drift %.2e" % (
                 Re, mode, entry["Ek_err_max"], entry["Ek_err_rms"], entry["enstrophy_err_max"],
-                entry["enstrophy_err_rms"]))
+                entry["enstrophy_err_rms"], entry["mass_drift_max"], entry["energy_drift_max"]))
             s.close()
         res_run["reference"] = ref_diag[Re]
         post[str(Re)] = res_run

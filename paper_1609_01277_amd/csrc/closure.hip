@@ -50,6 +50,9 @@ struct sbli_net {
     int wgrad_wg = kWgradWg;
     double* loss_part = nullptr;
     double* loss = nullptr;
+    int conservative = 0;            // remove each output field's box mean in sbli_net_forward
+    double* mean_part = nullptr;     // box-mean partial sums [max_batch * 5][chunks]
+    float* mean_val = nullptr;       // box means [max_batch * 5]
     std::string err;
 };
 
@@ -90,7 +93,7 @@ extern "C" int sbli_net_destroy(sbli_net* net) {
     }
     void* ptrs[] = {net->params, net->grads, net->adam_m, net->adam_v, net->stats, net->x, net->h1, net->h2,
                     net->dy, net->d2, net->d1, net->pre1, net->pre2, net->y, net->wpart, net->bpart, net->loss_part,
-                    net->loss};
+                    net->loss, net->mean_part, net->mean_val};
     for (void* p : ptrs) release(p);
     delete net;
     if (first != hipSuccess) return nfail(nullptr, SBLI_ERR_HIP, "sbli_net_destroy: %s", hipGetErrorString(first));
@@ -154,6 +157,8 @@ extern "C" int sbli_net_create(int n, int max_batch, void* hip_stream, sbli_net*
     alloc((void**)&net->bpart, sizeof(float) * (size_t)kBiasWg * 32);
     alloc((void**)&net->loss_part, sizeof(double) * nblk(NP));
     alloc((void**)&net->loss, sizeof(double));
+    alloc((void**)&net->mean_part, sizeof(double) * (size_t)max_batch * 5 * nblk(net->P, kBoxMeanChunk));
+    alloc((void**)&net->mean_val, sizeof(float) * (size_t)max_batch * 5);
     if (e == hipSuccess) e = hipStreamSynchronize(net->stream);
     if (e != hipSuccess) {
         nfail(nullptr, e == hipErrorOutOfMemory ? SBLI_ERR_ALLOC : SBLI_ERR_HIP, "sbli_net_create: %s",
@@ -310,7 +315,22 @@ extern "C" int sbli_net_forward(sbli_net* net, const float* q, int batch, float*
     if (rc != SBLI_OK) return rc;
     const int64_t NP = (int64_t)batch * net->P;
     destandardize_kernel<<<nblk(NP), 256, 0, net->stream>>>(net->y, net->P, batch, net->stats + 10, out);
+    if (net->conservative) {
+        const int nchunks = (int)nblk(net->P, kBoxMeanChunk), nbf = 5 * batch;
+        box_mean_partial_kernel<<<(unsigned)nchunks * (unsigned)nbf, 256, 0, net->stream>>>(out, net->P, nchunks,
+                                                                                             net->mean_part);
+        box_mean_final_kernel<<<nblk(nbf, 64), 64, 0, net->stream>>>(net->mean_part, nchunks, nbf, net->P,
+                                                                      net->mean_val);
+        box_mean_subtract_kernel<<<nblk((int64_t)nbf * net->P), 256, 0, net->stream>>>(out, net->P, nbf, net->mean_val);
+    }
     NHIP_TRY(net, hipGetLastError());
+    return SBLI_OK;
+}
+
+extern "C" int sbli_net_set_conservative(sbli_net* net, int on) {
+    if (!net) return nfail(nullptr, SBLI_ERR_ARG, "sbli_net_set_conservative: net is NULL");
+    if (on != 0 && on != 1) return nfail(net, SBLI_ERR_ARG, "sbli_net_set_conservative: on must be 0 or 1");
+    net->conservative = on;
     return SBLI_OK;
 }
 

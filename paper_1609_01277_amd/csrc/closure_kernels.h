@@ -136,6 +136,48 @@ __global__ void __launch_bounds__(256) destandardize_kernel(const float* __restr
     for (int c = 0; c < 5; ++c) out[(b * 5 + c) * P + p] = y[id * 8 + c] * mean_std[5 + c] + mean_std[c];
 }
 
+// Box mean of every (sample, field) plane of a planar [B][5][P] array, removed
+// in place: the closure term then adds nothing to the box totals of mass,
+// momentum and energy, as the exact closure term does (both residuals are
+// conservative and the filter keeps totals).  Three steps, each in a fixed
+// order, so the result is deterministic: FP64 partial sums of kBoxMeanChunk
+// points per workgroup, one mean per (sample, field), the subtraction.
+constexpr int kBoxMeanChunk = 4096;
+__global__ void __launch_bounds__(256) box_mean_partial_kernel(const float* __restrict__ a, int64_t P, int nchunks,
+                                                               double* __restrict__ part) {
+    // one workgroup per (sample * 5 + field, chunk), chunks fastest
+    const int chunk = (int)(blockIdx.x % (unsigned)nchunks);
+    const int64_t bf = blockIdx.x / (unsigned)nchunks;
+    const float* src = a + bf * P;
+    const int64_t lo = (int64_t)chunk * kBoxMeanChunk;
+    const int64_t hi = lo + kBoxMeanChunk < P ? lo + kBoxMeanChunk : P;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += (double)src[i];
+    __shared__ double ss[256];
+    ss[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) ss[threadIdx.x] += ss[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[bf * nchunks + chunk] = ss[0];
+}
+// one thread per (sample, field): the partials in chunk order
+__global__ void __launch_bounds__(64) box_mean_final_kernel(const double* __restrict__ part, int nchunks, int nbf,
+                                                            int64_t P, float* __restrict__ mean) {
+    const int bf = blockIdx.x * blockDim.x + threadIdx.x;
+    if (bf >= nbf) return;
+    double s = 0.0;
+    for (int k = 0; k < nchunks; ++k) s += part[(int64_t)bf * nchunks + k];
+    mean[bf] = (float)(s / (double)P);
+}
+__global__ void __launch_bounds__(256) box_mean_subtract_kernel(float* __restrict__ a, int64_t P, int nbf,
+                                                                const float* __restrict__ mean) {
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= (int64_t)nbf * P) return;
+    a[id] -= mean[id / P];
+}
+
 // ---------------------------------------------------------------------------
 // Implicit-GEMM convolution on MFMA (v_mfma_f32_32x32x16_bf16).
 //   out[b][p][o] = sum_kk W[o][kk] * in[b][p + off(tap(kk))][c(kk)]

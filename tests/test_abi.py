@@ -125,3 +125,4 @@ def test_closure_kernel_exports_validate_arguments(lib):
     assert L.sbli_adam_step(d, d, d, d, 0, 1e-3, 1, None) == sbli.SBLI_OK
     assert L.sbli_gelu_bwd(d, d, -1, d, None) == ERR
     assert L.sbli_gelu_bwd(d, d, 0, d, None) == sbli.SBLI_OK
+    assert L.sbli_net_set_conservative(None, 1) == ERR and "NULL" in msg()

@@ -137,6 +137,33 @@ def test_forward_and_gradients_match_oracle():
         assert rel_norm(db, rb) <= TOL_BF16, (li, rel_norm(db, rb))
 
 
+def test_conservative_forward_removes_box_means():
+    # batch of two different samples: the conservative output is the plain output minus
+    # each (sample, field) box mean, against the oracle's output with its box means removed
+    sbli, closure, torch = _mods()
+    n = 32
+    q, t, layers, stats = make_case(n)
+    q2 = np.concatenate([q, make_case(n, seed=5)[0]])
+    net = closure.ClosureNet(n, 2)
+    net.set_params(closure.join_params(layers).astype(np.float32))
+    net.set_stats(stats)
+    qd = torch.from_numpy(q2).cuda()
+    plain = net.forward(qd).cpu().numpy().astype(np.float64)
+    net.set_conservative(True)
+    cons = net.forward(qd).cpu().numpy().astype(np.float64)
+    net.set_conservative(False)
+    assert np.array_equal(net.forward(qd).cpu().numpy().astype(np.float64), plain)
+    scale = np.abs(plain).max()
+    # what the GPU removed is its own output's box mean (FP64 sums, one FP32 rounding)
+    assert np.abs(cons - nn.remove_box_mean(plain)).max() <= 1e-6 * scale
+    assert np.abs(cons.mean(axis=(2, 3, 4))).max() <= 1e-6 * scale
+    for b in range(2):
+        ref_out = oracle_pass(q2[b:b + 1], t, layers, stats)[0]
+        ref = nn.remove_box_mean(ref_out[None] if ref_out.ndim == 4 else ref_out)
+        assert np.abs(cons[b:b + 1] - ref.reshape(cons[b:b + 1].shape)).max() <= TOL_BF16 * np.abs(ref_out).max()
+    assert closure._L().sbli_net_set_conservative(net.net, 2) == sbli.SBLI_ERR_ARG
+
+
 def test_adam_step_matches_oracle():
     sbli, closure, torch = _mods()
     n = 32

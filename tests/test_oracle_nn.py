@@ -176,3 +176,17 @@ def test_adam_second_step_closed_forms():
     mh = (1 - b1) * (b1 * b1 - b1 + 1) / (1 - b1 ** 3) * g1
     vh = (1 - b2) * (b2 * b2 + b2 + 1) / (1 - b2 ** 3) * g1 * g1
     assert np.abs(p3 - (p2 - lr * mh / (np.sqrt(vh) + eps))).max() < 1e-14
+
+
+def test_remove_box_mean_on_constant_and_zero_mean_fields():
+    # a constant field (its own value per sample and field) has nothing left; a field
+    # of whole periods of sines has zero box mean and is unchanged; the two add
+    n = 12
+    rng = np.random.default_rng(3)
+    const = rng.uniform(-5, 5, size=(2, 5, 1, 1, 1)) * np.ones((2, 5, n, n, n))
+    x = np.arange(n) * 2 * np.pi / n
+    wave = np.sin(x)[None, None, None, None, :] * np.cos(2 * x)[None, None, :, None, None] * np.ones((2, 5, n, n, n))
+    wave *= rng.uniform(0.5, 2.0, size=(2, 5, 1, 1, 1))
+    assert np.abs(nn.remove_box_mean(const)).max() <= 1e-14
+    assert np.abs(nn.remove_box_mean(wave) - wave).max() <= 1e-14
+    assert np.abs(nn.remove_box_mean(const + wave) - wave).max() <= 1e-13
