@@ -334,6 +334,16 @@ def main():
         # bytes read plus bytes written per copy, over its average duration
         log("copied %d MiB x 5: %.3f ms per copy, %.0f GB/s read + write" % (
             args.calibrate_copy, ms, 2 * n * 8 / (ms * 1e-3) / 1e9))
+        # streaming reads alone (a sum) and writes alone (a fill) of the same size
+        for name, op in (("read (sum)", lambda: src.sum()), ("write (fill)", lambda: dst.fill_(2.0))):
+            op()
+            e0.record()
+            for _ in range(5):
+                op()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 5
+            log("%s of %d MiB: %.3f ms, %.0f GB/s" % (name, args.calibrate_copy, ms, n * 8 / (ms * 1e-3) / 1e9))
         return
     from paper_1609_01277_amd import build as libbuild
     if not libbuild.is_current():
