@@ -302,6 +302,8 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=256)
     ap.add_argument("--closure-only", action="store_true",
                     help="only time the learned closure's kernels (64^3, batch 4) and exit")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only time the 64-box FP32 ensemble (graph replay against box-by-box stepping) and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -354,6 +356,9 @@ def main():
 
     if args.closure_only:
         print(json.dumps(measure_closure(torch)), flush=True)
+        return
+    if args.batch_only:
+        print(json.dumps(measure_batch(sbli, torch, args.steps)), flush=True)
         return
     log("main: TGV %d^3 %s order %d, %d steps after %d warm-up" % (args.n, args.dtype, args.order,
                                                                   args.steps, args.warmup))
