@@ -807,7 +807,7 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
     if (rc != SBLI_OK) return rc;
     if (reps < 1) return bfail(b, SBLI_ERR_ARG, "sbli_batch_autotune: reps must be >= 1");
     const int nv = b->dtype == SBLI_F64 ? StageDispatch<double>::count(b->r) : StageDispatch<float>::count(b->r);
-    const int zc[4] = {128, 64, 32, 16};
+    const int zc[6] = {128, 96, 64, 48, 32, 16};
     hipEvent_t e0, e1;
     BHIP_TRY(b, hipEventCreate(&e0));
     BHIP_TRY(b, hipEventCreate(&e1));
@@ -816,7 +816,7 @@ extern "C" int sbli_batch_autotune(sbli_batch* b, void* q, void* q_tmp, void* dq
     hipError_t err = hipSuccess;
     // a failure ends both loops; rc and err then hold it
     for (int v = 0; v < nv && rc == SBLI_OK && err == hipSuccess; ++v)
-        for (int zi = 0; zi < 4; ++zi) {
+        for (int zi = 0; zi < 6; ++zi) {
             b->variant = v;
             b->zmax = zc[zi];
             rc = batch_build_table(b);
