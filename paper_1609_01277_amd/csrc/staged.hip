@@ -13,7 +13,10 @@ static void staged_run(const StagedArgs& a, const T* qin, T* dq, T* qout, T* nf)
         return (unsigned)(kStagedXcds * ((units + kStagedXcds - 1) / kStagedXcds));
     };
     {
-        constexpr int TN = kStagedTile;
+        // The nested-field step in 32x32 tiles where the register and LDS budget allows
+        // (every radius in FP32, up to R = 4 in FP64): each tile then fetches its R-wide
+        // x-arms, 32-byte row pieces of 128-byte lines, for four times as many own points.
+        constexpr int TN = (sizeof(T) == 8 && R > 4) ? kStagedTile : 2 * kStagedTile;
         const int tx = (c.n[0] + TN - 1) / TN, ty = (c.n[1] + TN - 1) / TN;
         const int zn = kNestedRun;
         staged_nested_zring_kernel<T, R, TN><<<grid_of(tx * ty, zn), TN * TN, 0, a.stream>>>(qin, nf, c, tx, ty, zn);
