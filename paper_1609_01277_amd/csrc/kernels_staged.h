@@ -26,9 +26,11 @@
 
 namespace sbli {
 
-// Both steps run in tiles: a workgroup owns a kStagedTile x kStagedTile tile of
-// (x, y) columns and a run of zchunk z-planes (the residual step runs one plane
-// per workgroup, the nested-field step runs of kNestedRun; see staged_unit).  Per
+// Both steps run in tiles: a workgroup owns a square tile of (x, y) columns
+// (kStagedTile wide in the residual step; twice that in the nested-field step
+// where registers and LDS allow, see staged.hip) and a run of zchunk z-planes (the
+// residual step runs one plane per workgroup, the nested-field step runs of
+// kNestedRun; see staged_unit).  Per
 // plane it stages what the x/y stencils read into LDS, so every element is
 // loaded once instead of once per neighbour that needs it.  The z neighbours of
 // the thread's own column come from memory in the residual step and from a
